@@ -1,0 +1,76 @@
+"""Planted mistakes in a copy of the oracle must each fail some pin.
+
+Every mutant is a plausible slip (a wrong shift, a dropped term, a swapped
+symbol, a relaxed padding rule, an off-by-one offset). The oracle source is
+copied to a temporary directory, edited there and compiled with gcc; the
+checked-in oracle is never modified.
+"""
+import os
+
+import pytest
+
+import oracle
+from oracle import build as obuild
+import test_oracle as pins
+
+MUTANTS = {
+    "enc_second_shift": ("(s[i + 1] / 16));\n        p[o++] = oracle_B(alphabet, ((s[i + 1] * 4)",
+                         "(s[i + 1] / 8));\n        p[o++] = oracle_B(alphabet, ((s[i + 1] * 4)"),
+    "enc_drop_third_term": ("+ (s[i + 2] / 64));", ");"),
+    "table_swap_62_63": ('"+/";', '"/+";'),
+    "url_swap": ("if (v == 62) return (uint8_t)'-';", "if (v == 62) return (uint8_t)'_';"),
+    "tail1_shift": ("p[o++] = oracle_B(alphabet, (s[i] * 16) % 64);",
+                    "p[o++] = oracle_B(alphabet, (s[i] * 4) % 64);"),
+    "drop_one_pad": ("        }\n        p[o++] = '=';\n    }\n    return o;", "        }\n    }\n    return o;"),
+    "dec_first_byte": ("(uint8_t)((a * 4) + (b / 16));\n        if (c[i + 2]",
+                       "(uint8_t)((a * 4) + (b / 8));\n        if (c[i + 2]"),
+    "dec_third_byte": ("(uint8_t)(((cc * 64) % 256) + d);\n    }", "(uint8_t)(((cc * 16) % 256) + d);\n    }"),
+    "pad_slot2_relaxed": ("if (i == n - 2 && c[n - 1] == '=') return 1;", "if (i == n - 2) return 1;"),
+    "no_length_check": ("if (bad < 0 && n % 4 != 0) bad = n;\n    if (bad >= 0) {\n        *err_off",
+                        "if (bad >= 0) {\n        *err_off"),
+    "offset_off_by_one": ("if (!oracle_char_ok(c, n, i, inv)) return i;",
+                          "if (!oracle_char_ok(c, n, i, inv)) return i + 1;"),
+    "dec_no_early_stop": ("        if (c[i + 2] == '=') return o;\n", ""),
+}
+
+PIN_TESTS = [
+    lambda t1: pins.test_table1_alphabet(t1),
+    lambda t1: pins.test_base64url_variant(t1),
+    lambda t1: pins.test_example_encode_R0lG(),
+    lambda t1: pins.test_example_decode_gif(),
+    lambda t1: pins.test_appendix_c_example(),
+    lambda t1: pins.test_standard_examples_named_for_this_codec(),
+    lambda t1: pins.test_length_law(),
+    lambda t1: pins.test_padding_readings(),
+    lambda t1: pins.test_rejection_sweep_all_256_bytes(t1, oracle.STD),
+    lambda t1: pins.test_rejection_sweep_all_256_bytes(t1, oracle.URL),
+    lambda t1: pins.test_all_one_and_two_byte_tails(t1, oracle.URL),
+    lambda t1: pins.test_single_injected_offset_is_exact(),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path, table1):
+    old, new = MUTANTS[name]
+    src = open(obuild.SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    mut = tmp_path / "b64_oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    so = obuild.build(out=str(tmp_path / "liboracle_mut.so"), src=str(mut),
+                      extra_flags=["-Wno-unused-variable", "-Wno-unused-but-set-variable"])
+    caught = []
+    with oracle.using(so):
+        for k, t in enumerate(PIN_TESTS):
+            try:
+                t(table1)
+            except AssertionError:
+                caught.append(k)
+    assert caught, f"no pin caught mutant {name}"
+
+
+def test_unmutated_copy_passes_all_pins(tmp_path, table1):
+    so = obuild.build(out=str(tmp_path / "liboracle_copy.so"))
+    with oracle.using(so):
+        for t in PIN_TESTS:
+            t(table1)
+    assert os.path.exists(so)

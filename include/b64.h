@@ -1,0 +1,197 @@
+/*
+ * b64hip: base64 encoding and validating decoding on AMD Instinct MI355X
+ * (gfx950), behind a plain C ABI.
+ *
+ * Semantics follow Muła & Lemire, "Faster Base64 Encoding and Decoding using
+ * AVX2 Instructions" (arXiv 1704.00605):
+ *   - alphabet: Section 2, Table 1 (standard) and the base64url variant of
+ *     Section 2 (62 -> '-', 63 -> '_');
+ *   - encoding: Section 2, Algorithm 1, with one '=' per leftover byte;
+ *   - decoding: Section 2, Algorithm 2, where characters outside the alphabet
+ *     are rejected (Section 2, and the standard quoted in Appendix B).
+ * Where the paper leaves decoding lenient, this library is strict:
+ *   - '=' is accepted only as the last character, or as each of the last two
+ *     characters, of an input whose length is a multiple of 4;
+ *   - a length that is not a multiple of 4 is an error at offset n;
+ *   - the reported offset is the smallest offending index;
+ *   - non-zero leftover bits in the final quad are accepted unless the strict
+ *     flag (Appendix A) is requested.
+ *
+ * Conventions for every entry point:
+ *   - Buffers named src/dst/in_off/out_off/flags/out_len/err_off/workspace
+ *     are DEVICE pointers on the current HIP device, owned by the caller.
+ *     The library keeps no reference after the call's GPU work ends.
+ *   - Pointers documented as "host" are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the NULL stream).
+ *     Calls named *_ex/_async/_batch only enqueue work on that stream unless
+ *     documented otherwise; results are valid once the stream reaches them.
+ *   - src and dst must not overlap. Any alignment is accepted; 4-byte
+ *     aligned src and dst take the fastest path.
+ *   - Lengths and offsets are int64 (inputs above 2^32 bytes are supported).
+ *   - Return codes: >= 0 success (a length where documented);
+ *       B64_INVALID_INPUT (-1) decode found an invalid character or length;
+ *       B64_BAD_ARG (-2) null pointer with n > 0, n < 0, bad alphabet, too
+ *       small workspace, bad tuning values;
+ *       B64_HIP_ERROR (-3) a HIP runtime call failed.
+ *     b64_last_error() describes the most recent failure on this thread.
+ *   - No entry point allocates device memory during the call except the
+ *     synchronous b64_decode / b64_decode_ex, which on first use on a thread
+ *     and device allocate (once) a 64-byte result slot and a pinned
+ *     readback word that are then reused.
+ */
+#ifndef B64HIP_H
+#define B64HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define B64_OK 0
+#define B64_INVALID_INPUT (-1)
+#define B64_BAD_ARG (-2)
+#define B64_HIP_ERROR (-3)
+
+/* Alphabets (Section 2): Table 1, or base64url. */
+#define B64_ALPHABET_STD 0
+#define B64_ALPHABET_URL 1
+
+/* Decode/encode mode bits, OR-ed into the `alphabet` argument of the *_ex,
+ * *_async and batched entry points:
+ *   B64_MODE_STRICT  Appendix A: the leftover bits of a padded final quad
+ *                    must be zero; a violation is an error at the index of
+ *                    the character holding them (n-3 for "==", n-2 for "=").
+ *   B64_MODE_NOPAD   Section 2 (padding may be omitted when the size is
+ *                    known): encode writes no '='; decode accepts lengths
+ *                    with n mod 4 in {0, 2, 3}, treats '=' as invalid and
+ *                    reports n mod 4 == 1 as an error at offset n. */
+#define B64_MODE_STRICT 0x100
+#define B64_MODE_NOPAD 0x200
+
+/* Number of characters Algorithm 1 writes for n bytes: 4 * ceil(n / 3)
+ * (or 4 * floor(n / 3) + {0, 2, 3} with B64_MODE_NOPAD via b64_encoded_len_mode).
+ * Pure host function; returns B64_BAD_ARG for n < 0. */
+int64_t b64_encoded_len(int64_t n);
+int64_t b64_encoded_len_mode(int64_t n, int mode);
+
+/* Output capacity a decode of m characters may need: 3 * floor(m / 4)
+ * (+2 for the unpadded mode's trailing partial group). Pure host function. */
+int64_t b64_decoded_max(int64_t m);
+int64_t b64_decoded_max_mode(int64_t m, int mode);
+
+/* Algorithm 1 (Section 2): encode src[0, n) into dst[0, 4 * ceil(n / 3)),
+ * standard alphabet, padded. Runs on the NULL stream and waits for it.
+ * Returns the number of characters written. Never fails on content. */
+int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst);
+
+/* Algorithm 2 (Section 2) with validation: decode src[0, n) into dst, whose
+ * capacity must be b64_decoded_max(n). Standard alphabet. Runs on the NULL
+ * stream and waits for it. Returns the decoded length and sets *err_off = -1
+ * (err_off is a HOST pointer), or returns B64_INVALID_INPUT with *err_off =
+ * the first offending index (n when only the length is wrong). The contents
+ * of dst are unspecified after an error. */
+int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_off);
+
+/* As b64_encode with an alphabet (plus mode bits) and a stream. Only
+ * enqueues work: returns the output length immediately. */
+int64_t b64_encode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, void *stream);
+
+/* As b64_decode with an alphabet (plus mode bits) and a stream. Enqueues the
+ * decode on `stream`, then waits for that stream to read back the verdict.
+ * err_off is a HOST pointer. */
+int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_off, int alphabet,
+                      void *stream);
+
+/* Non-blocking decode. d_len and d_err are DEVICE int64 slots that receive
+ * (decoded length, -1) or (-1, first offending index) when the stream
+ * reaches the end of the work. Returns B64_OK once enqueued, or an argument /
+ * runtime error code. */
+int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, int64_t *d_len,
+                     int64_t *d_err, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched forms: N messages packed back to back. Message i is
+ * src[in_off[i], in_off[i+1]); in_off has N+1 non-decreasing int64 entries
+ * (in_off[0] may be > 0). Its output starts at dst + out_off[i].
+ * flags (nullable -> all B64_ALPHABET_STD) holds one alphabet byte per
+ * message: bit 0 selects the alphabet; B64_FLAG_STRICT / B64_FLAG_NOPAD set
+ * the per-message mode (decode: strict / unpadded; encode: unpadded).
+ * ------------------------------------------------------------------------ */
+#define B64_FLAG_URL 0x01
+#define B64_FLAG_STRICT 0x02
+#define B64_FLAG_NOPAD 0x04
+
+#define B64_DIR_ENCODE 0
+#define B64_DIR_DECODE 1
+
+/* Device exclusive scan of per-message output sizes: out_off[0] = 0 and
+ * out_off[i+1] - out_off[i] = 4 * ceil(len_i / 3) (encode) or
+ * 3 * floor(len_i / 4) (+2 if the message is unpadded; decode capacity).
+ * out_off has N+1 entries. Enqueued on `stream`. */
+int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *out_off,
+                          const uint8_t *flags, void *stream);
+
+/* Launch shape of the persistent batched kernels. A zero field means "use
+ * the default". block: threads per workgroup (64..1024, multiple of 64);
+ * units_per_lane: 12-byte (encode) / 16-character (decode) units each lane
+ * carries per step (1..8); grid: number of workgroups (0 = fill the chip);
+ * small_msg: messages at most this many units long are handed out whole to
+ * single lanes instead of being split across a wave (0 = default). */
+typedef struct b64_tune {
+    int32_t block;
+    int32_t units_per_lane;
+    int32_t grid;
+    int32_t small_msg;
+} b64_tune;
+
+/* Device workspace (bytes) the batched calls need for N messages. */
+int64_t b64_batch_workspace_bytes(int64_t N);
+
+/* Encode N messages in one persistent launch (after a device planning pass
+ * over the offsets). out_off must be the scan from b64_batch_out_offsets
+ * (or any per-message slots at least that large, 4-byte aligned for speed).
+ * out_len[i] receives the characters written for message i. workspace is a
+ * device buffer of b64_batch_workspace_bytes(N) bytes. tune may be NULL.
+ * Enqueued on `stream`. */
+int b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                     const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                     void *workspace, int64_t workspace_bytes, const b64_tune *tune, void *stream);
+
+/* Decode N messages in one persistent launch. Per message: out_len[i] is the
+ * decoded length or -1; err_off[i] is -1 or the first offending index
+ * RELATIVE TO THE MESSAGE START. out_off gives capacity slots (see
+ * b64_batch_out_offsets). Enqueued on `stream`. */
+int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                     const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                     int64_t *err_off, void *workspace, int64_t workspace_bytes,
+                     const b64_tune *tune, void *stream);
+
+/* Plain per-message form of the batched calls (the baseline the batched
+ * kernels are measured against): one single-buffer launch per message, all on
+ * `stream`. Offsets and flags are HOST arrays here; out_len / err_off are
+ * DEVICE arrays (err_off unused for encode and may be NULL). */
+int b64_encode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,
+                    const int64_t *h_out_off, const uint8_t *h_flags, int64_t *out_len, void *stream);
+int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,
+                    const int64_t *h_out_off, const uint8_t *h_flags, int64_t *out_len,
+                    int64_t *err_off, void *stream);
+
+/* Launch shape of the single-buffer kernels for one direction (0 encode,
+ * 1 decode): block size, units per lane (1, 2, 4 or 8) and, in the `grid`
+ * field, workgroups per compute unit. Zero fields keep the current value.
+ * Process-wide; meant for tuning sweeps. */
+int b64_set_single_tune(int dir, const b64_tune *t);
+
+/* Thread-local description of the last failure (never NULL). */
+const char *b64_last_error(void);
+
+/* Library/device information: number of compute units of the current device
+ * (used to size persistent grids), or B64_HIP_ERROR. */
+int b64_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* B64HIP_H */

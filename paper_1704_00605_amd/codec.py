@@ -1,0 +1,245 @@
+"""Torch-facing API of the gfx950 base64 codec.
+
+PyTorch only supplies device memory and streams: every function here passes
+tensor pointers and sizes to ``libb64hip.so`` (see ``include/b64.h``), whose
+HIP kernels do all the work (Algorithm 1 encoding and validating Algorithm 2
+decoding of Section 2 of the paper).
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (ALPHABET_STD, ALPHABET_URL, DIR_DECODE, DIR_ENCODE, FLAG_NOPAD, FLAG_STRICT,
+                   FLAG_URL, MODE_NOPAD, MODE_STRICT, B64Error, Tune, check, lib)
+
+__all__ = [
+    "encode", "decode", "decode_async", "encoded_len", "decoded_max", "batch_out_offsets",
+    "encode_batch", "decode_batch", "encode_each", "decode_each", "workspace_bytes", "set_single_tune",
+    "ALPHABET_STD", "ALPHABET_URL", "MODE_STRICT", "MODE_NOPAD", "FLAG_URL", "FLAG_STRICT",
+    "FLAG_NOPAD", "DIR_ENCODE", "DIR_DECODE", "Tune", "B64Error",
+]
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_u8(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError(f"{name} must be a uint8 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def _tune(t):
+    if t is None:
+        return None
+    if isinstance(t, Tune):
+        return ctypes.byref(t)
+    tt = Tune(**{k: int(v) for k, v in dict(t).items() if k in ("block", "units_per_lane", "grid", "small_msg")})
+    return ctypes.byref(tt)
+
+
+def encoded_len(n, mode=0):
+    return check(lib().b64_encoded_len_mode(int(n), int(mode)), "encoded_len")
+
+
+def decoded_max(m, mode=0):
+    return check(lib().b64_decoded_max_mode(int(m), int(mode)), "decoded_max")
+
+
+def encode(src, alphabet=ALPHABET_STD, out=None, stream=None):
+    """Encode a uint8 CUDA tensor; returns the characters (uint8 CUDA tensor).
+
+    ``alphabet`` may carry ``MODE_NOPAD``. Asynchronous on ``stream``."""
+    src = _dev_u8(src, "src")
+    n = src.numel()
+    m = encoded_len(n, alphabet & ~0xff)
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.uint8, device=src.device)
+    else:
+        _dev_u8(out, "out")
+        if out.numel() < m:
+            raise ValueError("out is too small")
+    r = lib().b64_encode_ex(_ptr(src), n, _ptr(out), int(alphabet), _stream(stream))
+    check(r, "b64_encode_ex")
+    return out[:m]
+
+
+def decode(src, alphabet=ALPHABET_STD, out=None, stream=None):
+    """Validating decode of a uint8 CUDA tensor of characters.
+
+    Returns ``(bytes_tensor, -1)`` on success or ``(None, err_off)`` with the
+    first offending index. Waits for ``stream`` to read the verdict."""
+    src = _dev_u8(src, "src")
+    n = src.numel()
+    cap = decoded_max(n, alphabet & ~0xff)
+    if out is None:
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=src.device)
+    else:
+        _dev_u8(out, "out")
+        if out.numel() < cap:
+            raise ValueError("out is too small")
+    err = ctypes.c_int64(-1)
+    r = lib().b64_decode_ex(_ptr(src), n, _ptr(out), ctypes.byref(err), int(alphabet), _stream(stream))
+    check(r, "b64_decode_ex")
+    if r < 0:
+        return None, err.value
+    return out[:r], -1
+
+
+def decode_async(src, out, result, alphabet=ALPHABET_STD, stream=None):
+    """Non-blocking decode: ``result`` is an int64 CUDA tensor of 2 slots that
+    receives (length | -1, -1 | first offending index)."""
+    src = _dev_u8(src, "src")
+    _dev_u8(out, "out")
+    if result.dtype != torch.int64 or result.numel() < 2 or not result.is_cuda:
+        raise TypeError("result must be an int64 CUDA tensor with 2 slots")
+    rp = result.data_ptr()
+    r = lib().b64_decode_async(_ptr(src), src.numel(), _ptr(out), int(alphabet),
+                               ctypes.c_void_p(rp), ctypes.c_void_p(rp + 8), _stream(stream))
+    check(r, "b64_decode_async")
+
+
+def set_single_tune(direction, block=0, units_per_lane=0, blocks_per_cu=0):
+    t = Tune(block=block, units_per_lane=units_per_lane, grid=blocks_per_cu, small_msg=0)
+    check(lib().b64_set_single_tune(int(direction), ctypes.byref(t)), "b64_set_single_tune")
+
+
+# ----------------------------------------------------------------- batches --
+
+def _i64_dev(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int64 CUDA tensor")
+    return t
+
+
+def workspace_bytes(N):
+    return check(lib().b64_batch_workspace_bytes(int(N)), "workspace_bytes")
+
+
+def batch_out_offsets(direction, in_off, flags=None, stream=None):
+    """Device exclusive scan of the per-message output sizes (N+1 int64)."""
+    in_off = _i64_dev(in_off, "in_off")
+    N = in_off.numel() - 1
+    out_off = torch.empty(N + 1, dtype=torch.int64, device=in_off.device)
+    r = lib().b64_batch_out_offsets(int(direction), _ptr(in_off), N, _ptr(out_off),
+                                    _ptr(flags), _stream(stream))
+    check(r, "b64_batch_out_offsets")
+    return out_off
+
+
+class Workspace:
+    """A reusable device workspace for the batched calls (grows on demand,
+    outside the launch path)."""
+
+    def __init__(self, device=None):
+        self.buf = None
+        self.device = device
+
+    def get(self, N, device):
+        need = workspace_bytes(N)
+        if self.buf is None or self.buf.numel() < need or self.buf.device != device:
+            self.buf = torch.empty(need, dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws(ws, N, device):
+    if ws is None:
+        ws = _default_ws.setdefault(device, Workspace(device))
+    return ws.get(N, device)
+
+
+def encode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, tune=None,
+                 workspace=None, stream=None, total_out=None):
+    """Encode N packed messages in one persistent launch.
+
+    Returns ``(dst, out_off, out_len)``. ``total_out`` (host int, the last
+    entry of out_off) avoids a device read when ``dst`` is allocated here."""
+    src = _dev_u8(src, "src")
+    in_off = _i64_dev(in_off, "in_off")
+    N = in_off.numel() - 1
+    dev = src.device
+    if out_off is None:
+        out_off = batch_out_offsets(DIR_ENCODE, in_off, flags, stream)
+    if dst is None:
+        tot = int(out_off[-1].item()) if total_out is None else int(total_out)
+        dst = torch.empty(max(tot, 1), dtype=torch.uint8, device=dev)
+    if out_len is None:
+        out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    ws = _ws(workspace, N, dev)
+    r = lib().b64_encode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off), _ptr(flags),
+                               _ptr(out_len), _ptr(ws), ws.numel(), _tune(tune), _stream(stream))
+    check(r, "b64_encode_batch")
+    return dst, out_off, out_len[:N]
+
+
+def decode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, err_off=None,
+                 tune=None, workspace=None, stream=None, total_out=None):
+    """Decode N packed messages in one persistent launch.
+
+    Returns ``(dst, out_off, out_len, err_off)``; per message out_len is the
+    length or -1 and err_off is -1 or the offset inside the message."""
+    src = _dev_u8(src, "src")
+    in_off = _i64_dev(in_off, "in_off")
+    N = in_off.numel() - 1
+    dev = src.device
+    if out_off is None:
+        out_off = batch_out_offsets(DIR_DECODE, in_off, flags, stream)
+    if dst is None:
+        tot = int(out_off[-1].item()) if total_out is None else int(total_out)
+        dst = torch.empty(max(tot, 1), dtype=torch.uint8, device=dev)
+    if out_len is None:
+        out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    if err_off is None:
+        err_off = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    ws = _ws(workspace, N, dev)
+    r = lib().b64_decode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off), _ptr(flags),
+                               _ptr(out_len), _ptr(err_off), _ptr(ws), ws.numel(), _tune(tune),
+                               _stream(stream))
+    check(r, "b64_decode_batch")
+    return dst, out_off, out_len[:N], err_off[:N]
+
+
+def _host_i64(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_u8(a):
+    import numpy as np
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def encode_each(src, h_in_off, h_out_off, dst, out_len, h_flags=None, stream=None):
+    """Baseline: one single-buffer launch per message (host offsets)."""
+    a, pa = _host_i64(h_in_off)
+    b, pb = _host_i64(h_out_off)
+    f, pf = _host_u8(h_flags)
+    r = lib().b64_encode_each(_ptr(src), pa, a.size - 1, _ptr(dst), pb, pf, _ptr(out_len), _stream(stream))
+    check(r, "b64_encode_each")
+
+
+def decode_each(src, h_in_off, h_out_off, dst, out_len, err_off, h_flags=None, stream=None):
+    """Baseline: one single-buffer launch per message (host offsets)."""
+    a, pa = _host_i64(h_in_off)
+    b, pb = _host_i64(h_out_off)
+    f, pf = _host_u8(h_flags)
+    r = lib().b64_decode_each(_ptr(src), pa, a.size - 1, _ptr(dst), pb, pf, _ptr(out_len),
+                              _ptr(err_off), _stream(stream))
+    check(r, "b64_decode_each")

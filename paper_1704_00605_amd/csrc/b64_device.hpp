@@ -1,0 +1,260 @@
+// Device-side building blocks of the gfx950 base64 codec.
+//
+// Work unit: one lane turns 12 input bytes into 16 characters (encode) or 16
+// characters into 12 bytes (decode); a wave of 64 lanes therefore moves 768 or
+// 1024 contiguous bytes per load instruction. This is the GPU shape of the
+// paper's vector outline (Section 4: load, unpack/translate, pack, store);
+// the AVX2 lane-crossing shuffles it needs on x86 have no counterpart here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace b64dev {
+
+// ---------------------------------------------------------------- tables --
+// Section 2, Table 1 (standard alphabet) and the base64url variant (values
+// 62 and 63 become '-' and '_').
+struct Tables {
+    uint8_t enc[2][64];   // value -> character, per alphabet
+    uint8_t dec[2][256];  // character -> value, 0x80 = not a symbol ('=' too)
+};
+
+constexpr Tables make_tables()
+{
+    Tables t{};
+    const char std64[] = "ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/";
+    for (int a = 0; a < 2; a++) {
+        for (int v = 0; v < 64; v++) {
+            char ch = std64[v];
+            if (a == 1 && v == 62) ch = '-';
+            if (a == 1 && v == 63) ch = '_';
+            t.enc[a][v] = (uint8_t)ch;
+        }
+        for (int c = 0; c < 256; c++) t.dec[a][c] = 0x80;
+        for (int v = 0; v < 64; v++) t.dec[a][t.enc[a][v]] = (uint8_t)v;
+    }
+    return t;
+}
+
+constexpr uint8_t INVALID = 0x80;
+constexpr unsigned long long NO_ERR = ~0ull;
+
+// Mode bits (per call or per message).
+constexpr int M_URL = 1;
+constexpr int M_STRICT = 2;
+constexpr int M_NOPAD = 4;
+
+// -------------------------------------------------------------- byte ops --
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
+{
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// (hi:lo) >> (8 * s) for s in 0..3
+__device__ __forceinline__ uint32_t alignb(uint32_t hi, uint32_t lo, uint32_t s)
+{
+    return __builtin_amdgcn_alignbyte(hi, lo, s);
+}
+
+// -------------------------------------------------------- encode (a2,a3) --
+// Algorithm 1 on one triple held big-endian in the low 24 bits of v: the four
+// 6-bit fields, most significant first, mapped through B (LDS table `tab`).
+__device__ __forceinline__ uint32_t enc_quad(uint32_t v, const uint8_t *tab)
+{
+    uint32_t a = tab[v >> 18];
+    uint32_t b = tab[(v >> 12) & 63];
+    uint32_t c = tab[(v >> 6) & 63];
+    uint32_t d = tab[v & 63];
+    return a | (b << 8) | (c << 16) | (d << 24);
+}
+
+// 12 bytes (little-endian dwords w0..w2) -> 16 characters (o0..o3).
+// v_perm gathers each 3-byte group into big-endian order: bytes (b0,b1,b2),
+// (b3,b4,b5), (b6,b7,b8), (b9,b10,b11).
+__device__ __forceinline__ void enc_unit(uint32_t w0, uint32_t w1, uint32_t w2, const uint8_t *tab,
+                                         uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3)
+{
+    o0 = enc_quad(perm(w0, w0, 0x0c000102u), tab);
+    o1 = enc_quad(perm(w0, w1, 0x0c070001u), tab);
+    o2 = enc_quad(perm(w1, w2, 0x0c060700u), tab);
+    o3 = enc_quad(perm(w2, w2, 0x0c010203u), tab);
+}
+
+// Final partial unit of a message: r bytes (1..12) at s. Writes the
+// characters of Algorithm 1 (including its tail: one leftover byte -> two
+// characters, two -> three, then '=' padding unless nopad) to q and returns
+// their number.
+__device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
+                                     const uint8_t *tab, int nopad)
+{
+    int o = 0;
+    for (int i = 0; i < r; i += 3) {
+        uint32_t b0 = s[i];
+        uint32_t b1 = (i + 1 < r) ? s[i + 1] : 0u;
+        uint32_t b2 = (i + 2 < r) ? s[i + 2] : 0u;
+        uint32_t v = (b0 << 16) | (b1 << 8) | b2;
+        int left = r - i;  // 1, 2 or >= 3
+        q[o++] = tab[v >> 18];
+        q[o++] = tab[(v >> 12) & 63];
+        if (left >= 2) q[o++] = tab[(v >> 6) & 63];
+        else if (!nopad) q[o++] = '=';
+        if (left >= 3) q[o++] = tab[v & 63];
+        else if (!nopad) q[o++] = '=';
+    }
+    return o;
+}
+
+// ------------------------------------------------------ decode (a7,a9) --
+// 16 characters (w0..w3) -> 12 bytes (o0..o2). Returns the OR of the 16
+// looked-up values: bit 7 set means some character is not a symbol.
+// Each quad (a,b,c,d) packs to the 24-bit value a<<18 | b<<12 | c<<6 | d,
+// whose three bytes (most significant first) are Algorithm 2's output bytes.
+__device__ __forceinline__ uint32_t dec_word(uint32_t w, const uint8_t *tab, uint32_t &t)
+{
+    uint32_t a = tab[w & 0xff];
+    uint32_t b = tab[(w >> 8) & 0xff];
+    uint32_t c = tab[(w >> 16) & 0xff];
+    uint32_t d = tab[w >> 24];
+    t = (a << 18) | (b << 12) | (c << 6) | d;
+    return a | b | c | d;
+}
+
+__device__ __forceinline__ uint32_t dec_unit(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                             const uint8_t *tab, uint32_t &o0, uint32_t &o1,
+                                             uint32_t &o2)
+{
+    uint32_t t0, t1, t2, t3;
+    uint32_t bad = dec_word(w0, tab, t0) | dec_word(w1, tab, t1) | dec_word(w2, tab, t2) |
+                   dec_word(w3, tab, t3);
+    o0 = perm(t1, t0, 0x06000102u);  // t0.b2 t0.b1 t0.b0 t1.b2
+    o1 = perm(t2, t1, 0x05060001u);  // t1.b1 t1.b0 t2.b2 t2.b1
+    o2 = perm(t3, t2, 0x04050600u);  // t2.b0 t3.b2 t3.b1 t3.b0
+    return bad;
+}
+
+// Index (0..15) of the first non-symbol among the 16 characters of a unit.
+__device__ __noinline__ int dec_first_bad(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                          const uint8_t *tab)
+{
+    uint32_t w[4] = {w0, w1, w2, w3};
+    for (int k = 0; k < 16; k++) {
+        uint32_t ch = (w[k >> 2] >> (8 * (k & 3))) & 0xff;
+        if (tab[ch] & INVALID) return k;
+    }
+    return 16;
+}
+
+// Final unit of a message of n characters: r characters (1..16) at c, which
+// are characters n-r .. n-1. Applies the padding rules ('=' only as the last
+// one or two characters of a length divisible by 4; unpadded mode: '='
+// invalid, n mod 4 == 1 is a length error), the optional strict leftover-bit
+// check (Appendix A), and writes the decoded bytes to q. Returns the first
+// offending index relative to c (r stands for "length error at n"), or -1;
+// *nout receives the number of bytes written (0 when an error was found).
+__device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64_t n,
+                                     uint8_t *__restrict__ q, const uint8_t *tab, int mode,
+                                     int *nout)
+{
+    const bool nopad = (mode & M_NOPAD) != 0;
+    int pads = 0;
+    if (!nopad && (n & 3) == 0 && r >= 1 && c[r - 1] == '=') {
+        pads = 1;
+        if (r >= 2 && c[r - 2] == '=') pads = 2;
+    }
+    *nout = 0;
+    for (int k = 0; k < r - pads; k++)
+        if (tab[c[k]] & INVALID) return k;
+    if (nopad ? ((n & 3) == 1) : ((n & 3) != 0)) return r;
+    // Appendix A (strict): leftover bits of a padded final quad must be zero.
+    if ((mode & M_STRICT) && pads == 2 && ((tab[c[r - 3]] * 16) & 255) != 0) return r - 3;
+    if ((mode & M_STRICT) && pads == 1 && ((tab[c[r - 2]] * 64) & 255) != 0) return r - 2;
+    int o = 0;
+    const int full = r & ~3;  // characters in complete groups of 4
+    for (int k = 0; k < full; k += 4) {
+        uint32_t a = c[k] == '=' ? 0u : tab[c[k]];
+        uint32_t b = c[k + 1] == '=' ? 0u : tab[c[k + 1]];
+        uint32_t cc = c[k + 2] == '=' ? 0u : tab[c[k + 2]];
+        uint32_t d = c[k + 3] == '=' ? 0u : tab[c[k + 3]];
+        uint32_t t = (a << 18) | (b << 12) | (cc << 6) | d;
+        q[o++] = (uint8_t)(t >> 16);
+        if (c[k + 2] != '=') q[o++] = (uint8_t)(t >> 8);
+        if (c[k + 3] != '=') q[o++] = (uint8_t)t;
+    }
+    if (nopad && (r & 3) >= 2) {  // trailing group of 2 or 3 characters
+        uint32_t a = tab[c[full]], b = tab[c[full + 1]];
+        uint32_t cc = (r & 3) == 3 ? tab[c[full + 2]] : 0u;
+        uint32_t t = (a << 18) | (b << 12) | (cc << 6);
+        q[o++] = (uint8_t)(t >> 16);
+        if ((r & 3) == 3) q[o++] = (uint8_t)(t >> 8);
+    }
+    *nout = o;
+    return -1;
+}
+
+// ------------------------------------------------------------ memory ops --
+// Loads of `count` bytes from any address p read the aligned dwords that
+// contain them; every such dword holds at least one byte of [p, p + count),
+// so it lies on a page that the buffer occupies.
+__device__ __forceinline__ void load12(const uint8_t *p, uint32_t &w0, uint32_t &w1, uint32_t &w2)
+{
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *d = (const uint32_t *)(a & ~(uintptr_t)3);
+    const uint32_t s = (uint32_t)(a & 3);
+    if (s == 0) {
+        w0 = d[0]; w1 = d[1]; w2 = d[2];
+    } else {
+        uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
+        w0 = alignb(d1, d0, s); w1 = alignb(d2, d1, s); w2 = alignb(d3, d2, s);
+    }
+}
+
+__device__ __forceinline__ void load16(const uint8_t *p, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                       uint32_t &w3)
+{
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *d = (const uint32_t *)(a & ~(uintptr_t)3);
+    const uint32_t s = (uint32_t)(a & 3);
+    if (s == 0) {
+        w0 = d[0]; w1 = d[1]; w2 = d[2]; w3 = d[3];
+    } else {
+        uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+        w0 = alignb(d1, d0, s); w1 = alignb(d2, d1, s); w2 = alignb(d3, d2, s);
+        w3 = alignb(d4, d3, s);
+    }
+}
+
+// Stores of a byte run at any address: whole aligned dwords where the run
+// covers them, byte/short stores for the partial dwords at either end, so no
+// byte outside [q, q + 4k) is written.
+__device__ __forceinline__ void store_edge_lo(uint8_t *q, uint32_t v, uint32_t nbytes)
+{  // low nbytes (1..3) of v at the 4-byte aligned address q
+    if (nbytes & 2) { *(uint16_t *)q = (uint16_t)v; q += 2; v >>= 16; }
+    if (nbytes & 1) { q[0] = (uint8_t)v; }
+}
+
+template <int K>
+__device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
+{
+    const uintptr_t a = (uintptr_t)q;
+    const uint32_t s = (uint32_t)(a & 3);
+    if (s == 0) {
+        uint32_t *d = (uint32_t *)q;
+#pragma unroll
+        for (int k = 0; k < K; k++) d[k] = o[k];
+        return;
+    }
+    // bytes land at offset s of the aligned window d[0 .. K]
+    uint32_t *d = (uint32_t *)(a & ~(uintptr_t)3);
+    const uint32_t sh = 4 - s;  // realign: window dword j = (o[j] : o[j-1]) >> 8*sh
+    // head: high (4 - s) bytes of d[0] get the first (4 - s) bytes of o[0]
+    if (s == 1) { q[0] = (uint8_t)o[0]; *(uint16_t *)(q + 1) = (uint16_t)(o[0] >> 8); }
+    else if (s == 2) { *(uint16_t *)q = (uint16_t)o[0]; }
+    else { q[0] = (uint8_t)o[0]; }
+#pragma unroll
+    for (int k = 1; k < K; k++) d[k] = alignb(o[k], o[k - 1], sh);
+    // tail: low s bytes of d[K] get the last s bytes of o[K-1]
+    store_edge_lo((uint8_t *)(d + K), o[K - 1] >> (8 * sh), s);
+}
+
+}  // namespace b64dev

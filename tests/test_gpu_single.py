@@ -1,0 +1,244 @@
+"""GPU parity of the single-buffer codec against the oracle (bit-exact:
+characters, bytes, return length and error offset), through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1704_00605_amd import codec, workloads
+
+pytestmark = pytest.mark.gpu
+
+STD, URL = codec.ALPHABET_STD, codec.ALPHABET_URL
+NOPAD, STRICT = codec.MODE_NOPAD, codec.MODE_STRICT
+DEV = "cuda:0"
+
+# sizes around lane units (12 B / 16 chars), waves, default tiles
+# (256 lanes x 4 units) and a ragged tail
+SIZES = sorted(set(list(range(0, 70)) + [95, 96, 97, 767, 768, 769, 1023, 1024, 1025,
+                                         12287, 12288, 12289, 16383, 16384, 16385,
+                                         3 * 4096 * 4 + 5, 200_003, 1_000_001]))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def rnd(n, seed):
+    return np.random.default_rng(seed).integers(0, 256, n, dtype=np.uint8)
+
+
+def oracle_mode(alphabet):
+    return alphabet & 0xff
+
+
+@pytest.mark.parametrize("alphabet", [STD, URL, STD | NOPAD, URL | NOPAD])
+def test_encode_matches_oracle(alphabet):
+    for n in SIZES:
+        x = rnd(n, n)
+        got = host(codec.encode(dev(x), alphabet))
+        if alphabet & NOPAD:
+            want = oracle.encode_nopad(x, alphabet & 0xff)
+        else:
+            want = oracle.encode(x, alphabet & 0xff)
+        assert np.array_equal(got, want), (n, alphabet)
+
+
+@pytest.mark.parametrize("alphabet", [STD, URL])
+def test_decode_valid_matches_oracle(alphabet):
+    for n in SIZES:
+        x = rnd(n, n + 1)
+        t = oracle.encode(x, alphabet)
+        out, err = codec.decode(dev(t), alphabet)
+        assert err == -1, (n, err)
+        assert np.array_equal(host(out), x), n
+
+
+def test_decode_unpadded_and_strict():
+    for n in SIZES[:80] + [1000, 1001, 1002, 50_000]:
+        x = rnd(n, 3 * n + 7)
+        t = oracle.encode_nopad(x)
+        out, err = codec.decode(dev(t), STD | NOPAD)
+        want = oracle.decode_nopad(t)
+        assert (err, -1 if out is None else out.numel()) == (want[1], want[0])
+        assert np.array_equal(host(out), want[2])
+        tp = oracle.encode(x)
+        out, err = codec.decode(dev(tp), STD | STRICT)
+        assert err == -1 and np.array_equal(host(out), x)
+    for s in [b"Zh==", b"Zm9=", b"Zm8=", b"Zg==", b"QUJD" * 5 + b"Zh==", b"Z@==", b"QUJD" * 7 + b"Zm9="]:
+        want = oracle.decode_strict(s)
+        out, err = codec.decode(dev(np.frombuffer(s, np.uint8)), STD | STRICT)
+        assert (out.numel() if out is not None else -1, err) == want[:2], s
+    for s in [b"Zg", b"Zm9", b"Zg=", b"Z", b"ZmZmZ", b"QUJDRA", b"QUJD=A"]:
+        want = oracle.decode_nopad(s)
+        out, err = codec.decode(dev(np.frombuffer(s, np.uint8)), STD | NOPAD)
+        assert (out.numel() if out is not None else -1, err) == want[:2], s
+
+
+def test_padding_and_length_readings():
+    cases = [b"", b"Zg==", b"Zh==", b"Zm8=", b"Zg==AAAA", b"AB=C", b"Zg=", b"Z===", b"====",
+             b"=AAA", b"A", b"AB", b"ABC", b"AB\x80D", b"AB D", b"A@C", b"QUJD" * 4 + b"Zg==",
+             b"QUJD" * 4 + b"Z===", b"QUJD" * 4 + b"Zg=A", b"QUJD" * 3 + b"Zg==",
+             b"QUJD" * 8 + b"=", b"QUJD" * 8 + b"==", b"QUJD" * 5 + b"A", b"QU=D" * 5]
+    for s in cases:
+        want = oracle.decode(s)
+        out, err = codec.decode(dev(np.frombuffer(s, np.uint8)) if s else torch.empty(0, dtype=torch.uint8, device=DEV))
+        got_len = -1 if out is None else out.numel()
+        assert (got_len, err) == want[:2], s
+        if out is not None:
+            assert bytes(host(out)) == bytes(want[2])
+
+
+@pytest.mark.parametrize("alphabet", [STD, URL])
+def test_rejection_sweep_all_bytes_and_positions(alphabet):
+    """Every byte value at every position class of texts whose lengths put
+    the position in an interior unit, a tail unit and the padding quad."""
+    rng = np.random.default_rng(21)
+    for n_bytes in (30, 31, 32, 100, 3 * 64):
+        x = rng.integers(0, 256, n_bytes, dtype=np.uint8)
+        t = oracle.encode(x, alphabet)
+        m = t.size
+        positions = sorted(set([0, 1, 15, 16, 17, m // 2, m - 17, m - 16, m - 5, m - 4, m - 3, m - 2, m - 1]))
+        for pos in positions:
+            if not 0 <= pos < m:
+                continue
+            for b in range(256):
+                tt = t.copy()
+                tt[pos] = b
+                want = oracle.decode(tt, alphabet)
+                out, err = codec.decode(dev(tt), alphabet)
+                assert ((-1 if out is None else out.numel()), err) == want[:2], (n_bytes, pos, b)
+
+
+def test_injected_errors_and_minimum_offset():
+    rng = np.random.default_rng(5)
+    for n in [100, 1000, 12289, 100_000, 1_000_003]:
+        x = rnd(n, n)
+        t = oracle.encode(x)
+        for _ in range(6):
+            tt = t.copy()
+            k = int(rng.integers(1, 5))
+            pos = rng.integers(0, t.size, size=k)
+            for p in pos:
+                tt[p] = workloads.corruption_byte(int(rng.integers(0, 192)), 0, int(p), t.size)
+            want = oracle.decode(tt)
+            out, err = codec.decode(dev(tt))
+            assert ((-1 if out is None else out.numel()), err) == want[:2], (n, pos)
+
+
+@pytest.mark.parametrize("soff,doff", [(1, 0), (0, 1), (2, 3), (3, 2), (5, 7), (13, 15), (4, 8)])
+def test_misaligned_subbuffers(soff, doff):
+    for n in [0, 1, 2, 3, 11, 12, 13, 100, 4097, 100_001]:
+        x = rnd(n, n + soff)
+        big = torch.zeros(n + 64, dtype=torch.uint8, device=DEV)
+        big[soff:soff + n] = dev(x) if n else big[:0]
+        m = oracle.encoded_len(n)
+        outbig = torch.full((m + 64,), 0xAB, dtype=torch.uint8, device=DEV)
+        got = codec.encode(big[soff:soff + n], STD, out=outbig[doff:doff + m])
+        assert np.array_equal(host(got), oracle.encode(x)), (n, soff, doff)
+        ob = host(outbig)
+        assert np.all(ob[:doff] == 0xAB) and np.all(ob[doff + m:] == 0xAB)  # no stray writes
+        t = oracle.encode(x)
+        tb = torch.zeros(m + 64, dtype=torch.uint8, device=DEV)
+        tb[soff:soff + m] = dev(t) if m else tb[:0]
+        cap = oracle.decoded_max(m)
+        db = torch.full((cap + 64,), 0xCD, dtype=torch.uint8, device=DEV)
+        out, err = codec.decode(tb[soff:soff + m], STD, out=db[doff:doff + cap])
+        assert err == -1 and np.array_equal(host(out), x), (n, soff, doff)
+        dbh = host(db)
+        assert np.all(dbh[:doff] == 0xCD) and np.all(dbh[doff + n:] == 0xCD)
+
+
+def test_decode_writes_nothing_past_the_decoded_length():
+    for n in [1, 2, 4, 5, 100, 1001]:
+        x = rnd(n, 99 + n)
+        t = oracle.encode(x)
+        cap = oracle.decoded_max(t.size)
+        buf = torch.full((cap + 32,), 0x5A, dtype=torch.uint8, device=DEV)
+        out, err = codec.decode(dev(t), out=buf[:cap])
+        b = host(buf)
+        assert np.array_equal(b[:n], x) and np.all(b[n:] == 0x5A)
+
+
+def test_async_decode_slots():
+    res = torch.zeros(2, dtype=torch.int64, device=DEV)
+    for n in [0, 1, 50, 100_000]:
+        x = rnd(n, n)
+        t = oracle.encode(x)
+        tt = t.copy()
+        if t.size:
+            tt[t.size // 3] = ord("*")
+        for txt in (t, tt):
+            out = torch.empty(oracle.decoded_max(txt.size) + 1, dtype=torch.uint8, device=DEV)
+            src = dev(txt) if txt.size else torch.empty(0, dtype=torch.uint8, device=DEV)
+            codec.decode_async(src, out, res)
+            torch.cuda.synchronize()
+            want = oracle.decode(txt)
+            assert tuple(host(res)) == want[:2]
+
+
+def test_all_2_24_triples_closed_form():
+    i = np.arange(1 << 24, dtype=np.uint32)
+    buf = np.stack([(i >> 16) & 255, (i >> 8) & 255, i & 255], axis=1).astype(np.uint8).reshape(-1)
+    for alphabet in (STD, URL):
+        t = codec.encode(dev(buf), alphabet)
+        assert np.array_equal(host(t), oracle.encode(buf, alphabet))
+        out, err = codec.decode(t, alphabet)
+        assert err == -1 and torch.equal(out, dev(buf))
+
+
+def test_config1_one_mib_seed0():
+    w = workloads.single(1 << 20, seed=0)
+    x = w["payload"]
+    t = codec.encode(dev(x))
+    want = oracle.encode(x)
+    assert t.numel() == 1_398_104 and np.array_equal(host(t), want)
+    out, err = codec.decode(t)
+    assert err == -1 and np.array_equal(host(out), x)
+    tt = want.copy()
+    applied = workloads.corrupt_text(tt, np.array([0, tt.size]), [0], [w["corrupt_u"]], [w["corrupt_rank"]])
+    (_, pos, _b), = applied
+    ow = oracle.decode(tt)
+    assert ow[:2] == (-1, pos)
+    out, err = codec.decode(dev(tt))
+    assert (out, err) == (None, pos)
+
+
+def test_config2_one_gib_sampled():
+    """1 GiB at the benchmark's launch shape: round trip checked on the
+    device, sampled windows and the tail checked against the oracle, and the
+    injected byte at 99.9% of the text found at exactly its offset."""
+    n = 1 << 30
+    w = workloads.single_at_fraction(n, seed=1, frac=0.999)
+    x = dev(w["payload"])
+    t = codec.encode(x)
+    m = t.numel()
+    assert m == 1_431_655_768
+    rng = np.random.default_rng(123)
+    starts = [0, n - 3 * 1000 - (n % 3)] + list((rng.integers(0, n // 3 - 1000, 48) * 3))
+    xh = w["payload"]
+    th = t[:0]
+    for s in starts:
+        s = int(s)
+        seg = xh[s:s + 3000]
+        assert np.array_equal(host(t[s // 3 * 4: s // 3 * 4 + 4000]), oracle.encode(seg)), s
+    tail = xh[n - (n % 3) - 3000:]
+    assert np.array_equal(host(t[-oracle.encoded_len(tail.size):]), oracle.encode(tail))
+    del th
+    out, err = codec.decode(t)
+    assert err == -1 and out.numel() == n and torch.equal(out, x)
+    del out
+    pos = int(np.floor(0.999 * m))
+    assert pos == 1_430_224_112
+    b = workloads.corruption_byte(w["corrupt_rank"], 0, pos, m)
+    t[pos] = b
+    # oracle verdict on the quad-aligned window holding the byte
+    lo = (pos // 4) * 4 - 4000
+    ow = oracle.decode(host(t[lo:lo + 8000]))
+    assert ow[:2] == (-1, pos - lo)
+    out, err = codec.decode(t)
+    assert out is None and err == pos

@@ -1,0 +1,80 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+declared in include/b64.h, and its pure-host functions and argument checks
+behave as documented (no kernel is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1704_00605_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "b64.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(b64_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, f"binding lacks {n}"
+
+
+def test_library_is_gfx950_code_object():
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_length_functions(L):
+    for n in range(0, 100):
+        assert L.b64_encoded_len(n) == 4 * -(-n // 3)
+        assert L.b64_decoded_max(n) == 3 * (n // 4)
+        nopad = L.b64_encoded_len_mode(n, _lib.MODE_NOPAD)
+        assert nopad == 4 * (n // 3) + ((n % 3) + 1 if n % 3 else 0)
+        assert L.b64_decoded_max_mode(n, _lib.MODE_NOPAD) == 3 * (n // 4) + max(0, n % 4 - 1)
+    assert L.b64_encoded_len(-1) == _lib.BAD_ARG
+    assert L.b64_decoded_max(-5) == _lib.BAD_ARG
+    assert L.b64_encoded_len((1 << 40) + 1) == 4 * -(-((1 << 40) + 1) // 3)
+
+
+def test_argument_errors_need_no_gpu(L):
+    err = ctypes.c_int64(0)
+    assert L.b64_encode_ex(None, 0, None, 0, None) == 0
+    assert L.b64_encode_ex(None, 10, None, 0, None) == _lib.BAD_ARG
+    assert L.b64_encode_ex(None, 0, None, 7, None) == _lib.BAD_ARG
+    assert "alphabet" in _lib.last_error()
+    assert L.b64_encode_ex(None, -1, None, 0, None) == _lib.BAD_ARG
+    assert L.b64_decode_ex(None, 0, None, ctypes.byref(err), 0, None) == 0 and err.value == -1
+    assert L.b64_decode_ex(None, 8, None, None, 0, None) == _lib.BAD_ARG
+    assert L.b64_decode_ex(None, 0, None, ctypes.byref(err),
+                           _lib.MODE_STRICT | _lib.MODE_NOPAD, None) == _lib.BAD_ARG
+    assert L.b64_decode_async(None, 4, None, 0, None, None, None) == _lib.BAD_ARG
+    assert L.b64_batch_workspace_bytes(-1) == _lib.BAD_ARG
+    assert L.b64_batch_workspace_bytes(0) > 0
+    assert L.b64_batch_workspace_bytes(100000) >= 8 * 100001
+    assert L.b64_encode_batch(None, None, -1, None, None, None, None, None, 0, None, None) == _lib.BAD_ARG
+    assert L.b64_encode_batch(None, None, 0, None, None, None, None, None, 0, None, None) == 0
+    bad = _lib.Tune(block=100, units_per_lane=0, grid=0, small_msg=0)
+    assert L.b64_set_single_tune(0, ctypes.byref(bad)) == _lib.BAD_ARG
+    assert L.b64_set_single_tune(5, ctypes.byref(bad)) == _lib.BAD_ARG
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(_lib.B64Error):
+        _lib.lib()

@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "encode/decode GB/s & %HBM peak; batched vs per-msg launch; p50/p99 latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_single_1GiB.json")
 
 
 def parse():
@@ -38,7 +38,23 @@ def parse():
     ap.add_argument("--size", type=int, default=1 << 30, help="payload bytes (default 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=1024)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain int32 copy kernel (1 GiB in, 1 GiB out) three times; "
+                         "its HBM counter readings scale the codec's counter readings")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+
+    dev = torch.device("cuda:0")
+    a = torch.zeros((1 << 30) // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.add(a, 0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
+                      "launches": 3}), flush=True)
 
 
 def cpu_baseline(payload, text, sample_mib):
@@ -79,6 +95,9 @@ def cpu_baseline(payload, text, sample_mib):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "

@@ -135,9 +135,8 @@ int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *ou
 /* Launch shape of the persistent batched kernels. A zero field means "use
  * the default". block: threads per workgroup (64..1024, multiple of 64);
  * units_per_lane: 12-byte (encode) / 16-character (decode) units each lane
- * carries per step (1..8); grid: number of workgroups (0 = fill the chip);
- * small_msg: messages at most this many units long are handed out whole to
- * single lanes instead of being split across a wave (0 = default). */
+ * carries per step (1, 2, 4 or 8); grid: number of workgroups of the
+ * persistent launch (0 = 8 per compute unit); small_msg: reserved, 0. */
 typedef struct b64_tune {
     int32_t block;
     int32_t units_per_lane;
@@ -179,8 +178,9 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
 
 /* Launch shape of the single-buffer kernels for one direction (0 encode,
  * 1 decode): block size, units per lane (1, 2, 4 or 8) and, in the `grid`
- * field, workgroups per compute unit. Zero fields keep the current value.
- * Process-wide; meant for tuning sweeps. */
+ * field, workgroups per compute unit (1..4096, or -1 for one workgroup per
+ * tile, the default). Zero fields keep the current value. Process-wide;
+ * meant for tuning sweeps. */
 int b64_set_single_tune(int dir, const b64_tune *t);
 
 /* Thread-local description of the last failure (never NULL). */

@@ -199,15 +199,14 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
 
 // Decode src[0, n), n >= 1. Interior units [0, L) with L = (n - 1) / 16 hold
 // 16 characters that are all before the final one; unit L (1..16 characters)
-// carries the padding and length rules. The error slot and block counter
-// must hold (NO_ERR, 0) at launch; the last block to finish writes the
-// verdict to res_len / res_err and, with self_reset, restores the slot.
+// carries the padding and length rules. err_slot must hold ERR_NONE at
+// launch; it ends holding the smallest offending index (or ERR_NONE). The
+// lane of the final unit writes the decoded length to *len_slot when that
+// unit is valid. k_dec_final turns the pair into the verdict.
 template <bool ALIGNED, int UPL>
 __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, int mode,
-                                                     unsigned long long *err_slot,
-                                                     unsigned int *counter, int64_t *res_len,
-                                                     int64_t *res_err, int self_reset)
+                                                     unsigned long long *err_slot, int64_t *len_slot)
 {
     __shared__ uint32_t s_tab[64];
     lds_fill(s_tab, c_tab.dec[mode & M_URL], 256);
@@ -227,43 +226,32 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
         const int r = (int)(n - 16 * L);
         const int idx = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode, &nout);
         if (idx >= 0) atomicMin(err_slot, (unsigned long long)(16 * L + idx));
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int prev = atomicAdd(counter, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
-            const unsigned long long e = atomicOr(err_slot, 0ull);
-            if (e == NO_ERR) {
-                int64_t len;
-                if (mode & M_NOPAD) {
-                    len = 3 * (n / 4) + ((n & 3) ? (n & 3) - 1 : 0);
-                } else {
-                    const int pads = (src[n - 1] == '=') + (src[n - 1] == '=' && src[n - 2] == '=');
-                    len = 3 * (n / 4) - pads;
-                }
-                *res_len = len;
-                *res_err = -1;
-            } else {
-                *res_len = -1;
-                *res_err = (int64_t)e;
-            }
-            if (self_reset) {
-                *err_slot = NO_ERR;
-                *counter = 0u;
-            }
-        }
+        else *len_slot = 12 * L + nout;
     }
 }
 
-// Sets an asynchronous decode's device slots to (counter 0, NO_ERR), or to
-// the final verdict of an empty input.
+// Verdict of a single-buffer decode, run after k_dec_single on the same
+// stream: (length, -1) or (-1, first offending index). With reset, the error
+// slot is restored to ERR_NONE for the next call.
+__global__ void k_dec_final(unsigned long long *err_slot, const int64_t *len_slot, int64_t *out_len,
+                            int64_t *out_err, int reset)
+{
+    if (threadIdx.x == 0) {
+        const unsigned long long e = *err_slot;
+        const int64_t len = *len_slot;
+        if (e == ERR_NONE) { *out_len = len; *out_err = -1; }
+        else { *out_len = -1; *out_err = (int64_t)e; }
+        if (reset) *err_slot = ERR_NONE;
+    }
+}
+
+// Prepares an asynchronous decode's device slots: the error slot (which is
+// d_err itself) to ERR_NONE, or the final verdict of an empty input.
 __global__ void k_slots_init(int64_t *d_len, int64_t *d_err, int empty)
 {
     if (threadIdx.x == 0) {
         *d_len = 0;
-        *d_err = empty ? -1 : (int64_t)NO_ERR;
+        *d_err = empty ? -1 : (int64_t)ERR_NONE;
     }
 }
 
@@ -338,7 +326,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_reduce(const int64_t *__res
 
 // unit_off = exclusive scan of units per message (N + 1 entries), plus
 // per-message initialisation: encode out_len (known from the length);
-// decode out_len = 0 and err_off = INT64_MAX (the atomicMin sentinel).
+// decode out_len = 0 and err_off = ERR_NONE (the atomicMin sentinel).
 template <int DIR>
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
     const int64_t *__restrict__ in_off, int64_t N, const uint8_t *__restrict__ flags,
@@ -362,7 +350,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
                 out_len[i] = enc_len_of(len, fl & M_NOPAD);
             } else {
                 out_len[i] = 0;
-                err_off[i] = INT64_MAX;
+                err_off[i] = (int64_t)ERR_NONE;
             }
         }
         s += u[k];
@@ -593,7 +581,7 @@ __global__ void k_dec_batch_final(int64_t N, int64_t *__restrict__ out_len, int6
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t e = err_off[i];
-        if (e == INT64_MAX) err_off[i] = -1;
+        if (e == (int64_t)ERR_NONE) err_off[i] = -1;
         else out_len[i] = -1;
     }
 }
@@ -651,15 +639,20 @@ int device_cus(int *out)
 }
 
 // Launch shapes of the single-buffer kernels (settable for tuning sweeps).
+// Default: 512 lanes x 2 units per workgroup and one workgroup per tile
+// (blocks_per_cu == 0), the fastest shape of a sweep over block {256, 512,
+// 1024} x units {1, 2, 4, 8} x grid {2..64 per CU, one-shot} on MI355X for
+// both directions at 1 GiB.
 struct Shape {
-    std::atomic<int> block{256};
-    std::atomic<int> upl{4};
-    std::atomic<int> blocks_per_cu{8};
+    std::atomic<int> block{512};
+    std::atomic<int> upl{2};
+    std::atomic<int> blocks_per_cu{0};
 };
 Shape g_single[2];
 
-// Per-thread, per-device result slot of the synchronous decode:
-// [0] error slot (u64), [1] block counter (u32), [2] length, [3] error.
+// Per-thread, per-device result slots of the synchronous decode:
+// [0] error slot (u64, kept at ERR_NONE between calls), [1] length written by
+// the final unit, [2] verdict length, [3] verdict error offset.
 struct SyncSlot {
     int dev = -1;
     unsigned long long *d = nullptr;
@@ -677,7 +670,7 @@ int sync_slot(SyncSlot **out)
     s.dev = dev;
     HIP_TRY(hipMalloc((void **)&s.d, 64));
     HIP_TRY(hipHostMalloc((void **)&s.h, 16, hipHostMallocDefault));
-    unsigned long long init[4] = {NO_ERR, 0ull, 0ull, 0ull};
+    unsigned long long init[4] = {ERR_NONE, 0ull, 0ull, 0ull};
     HIP_TRY(hipMemcpy(s.d, init, sizeof init, hipMemcpyHostToDevice));
     t_slots.push_back(s);
     *out = &t_slots.back();
@@ -706,7 +699,8 @@ int single_grid(int dir, int64_t units, int *block, int *upl, int *grid)
     *upl = g_single[dir].upl.load();
     const int64_t per = (int64_t)(*block) * (*upl);
     int64_t tiles = (units + per - 1) / per;
-    int64_t cap = (int64_t)cus * g_single[dir].blocks_per_cu.load();
+    const int bpc = g_single[dir].blocks_per_cu.load();
+    int64_t cap = bpc ? (int64_t)cus * bpc : (int64_t)INT32_MAX;
     *grid = (int)std::max<int64_t>(1, std::min(tiles, cap));
     return B64_OK;
 }
@@ -725,14 +719,13 @@ void launch_enc_single(int upl, int grid, int block, const uint8_t *src, int64_t
 
 template <bool A>
 void launch_dec_single(int upl, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
-                       int mode, unsigned long long *slot, unsigned int *cnt, int64_t *rl,
-                       int64_t *re, int reset, hipStream_t s)
+                       int mode, unsigned long long *slot, int64_t *len_slot, hipStream_t s)
 {
     switch (upl) {
-    case 1: hipLaunchKernelGGL((k_dec_single<A, 1>), grid, block, 0, s, src, n, dst, mode, slot, cnt, rl, re, reset); break;
-    case 2: hipLaunchKernelGGL((k_dec_single<A, 2>), grid, block, 0, s, src, n, dst, mode, slot, cnt, rl, re, reset); break;
-    case 8: hipLaunchKernelGGL((k_dec_single<A, 8>), grid, block, 0, s, src, n, dst, mode, slot, cnt, rl, re, reset); break;
-    default: hipLaunchKernelGGL((k_dec_single<A, 4>), grid, block, 0, s, src, n, dst, mode, slot, cnt, rl, re, reset); break;
+    case 1: hipLaunchKernelGGL((k_dec_single<A, 1>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
+    case 2: hipLaunchKernelGGL((k_dec_single<A, 2>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
+    case 8: hipLaunchKernelGGL((k_dec_single<A, 8>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
+    default: hipLaunchKernelGGL((k_dec_single<A, 4>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
     }
 }
 
@@ -752,14 +745,16 @@ int enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, hipStr
     return B64_OK;
 }
 
+// Enqueues the decode kernel of src[0, n) (n >= 1); the error slot must hold
+// ERR_NONE. No verdict is formed here (see k_dec_final / k_dec_batch_final).
 int enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, unsigned long long *slot,
-                   unsigned int *cnt, int64_t *rl, int64_t *re, int reset, hipStream_t s)
+                   int64_t *len_slot, hipStream_t s)
 {
     int block, upl, grid;
     int rc = single_grid(1, (n - 1) / 16, &block, &upl, &grid);
     if (rc) return rc;
-    if (aligned4(src, dst)) launch_dec_single<true>(upl, grid, block, src, n, dst, mode, slot, cnt, rl, re, reset, s);
-    else launch_dec_single<false>(upl, grid, block, src, n, dst, mode, slot, cnt, rl, re, reset, s);
+    if (aligned4(src, dst)) launch_dec_single<true>(upl, grid, block, src, n, dst, mode, slot, len_slot, s);
+    else launch_dec_single<false>(upl, grid, block, src, n, dst, mode, slot, len_slot, s);
     LAUNCH_TRY();
     return B64_OK;
 }
@@ -849,9 +844,11 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
     rc = sync_slot(&sl);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    rc = enqueue_decode(src, n, dst, mode, sl->d, (unsigned int *)(sl->d + 1), (int64_t *)(sl->d + 2),
-                        (int64_t *)(sl->d + 3), 1, s);
+    rc = enqueue_decode(src, n, dst, mode, sl->d, (int64_t *)(sl->d + 1), s);
     if (rc) return rc;
+    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, sl->d, (const int64_t *)(sl->d + 1), (int64_t *)(sl->d + 2),
+                       (int64_t *)(sl->d + 3), 1);
+    LAUNCH_TRY();
     HIP_TRY(hipMemcpyAsync(sl->h, sl->d + 2, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const int64_t len = sl->h[0], err = sl->h[1];
@@ -881,8 +878,11 @@ int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, 
     hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, n == 0 ? 1 : 0);
     LAUNCH_TRY();
     if (n == 0) return B64_OK;
-    return enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, (unsigned int *)d_len, d_len,
-                          d_err, 0, s);
+    rc = enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, d_len, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, (unsigned long long *)d_err, d_len, d_len, d_err, 0);
+    LAUNCH_TRY();
+    return B64_OK;
 }
 
 int b64_set_single_tune(int dir, const b64_tune *t)
@@ -900,8 +900,9 @@ int b64_set_single_tune(int dir, const b64_tune *t)
         g_single[dir].upl = t->units_per_lane;
     }
     if (t->grid) {
-        if (t->grid < 1 || t->grid > 4096) return fail(B64_BAD_ARG, "blocks per CU must be 1..4096");
-        g_single[dir].blocks_per_cu = t->grid;
+        // blocks per CU; -1 selects one workgroup per tile
+        if (t->grid < -1 || t->grid > 4096) return fail(B64_BAD_ARG, "blocks per CU must be -1 or 1..4096");
+        g_single[dir].blocks_per_cu = t->grid < 0 ? 0 : t->grid;
     }
     return B64_OK;
 }
@@ -1038,13 +1039,8 @@ __global__ void k_each_init(int64_t N, int64_t *__restrict__ d_len, int64_t *__r
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         d_len[i] = 0;
-        d_err[i] = (int64_t)NO_ERR;
+        d_err[i] = (int64_t)ERR_NONE;
     }
-}
-
-__global__ void k_each_empty(int64_t *d_len, int64_t *d_err)
-{
-    if (threadIdx.x == 0) { *d_len = 0; *d_err = -1; }
 }
 
 int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,
@@ -1060,16 +1056,13 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
     for (int64_t i = 0; i < N; i++) {
         const int64_t n = h_in_off[i + 1] - h_in_off[i];
         const int fl = h_flags ? h_flags[i] : 0;
-        if (n == 0) {
-            hipLaunchKernelGGL(k_each_empty, 1, 64, 0, s, out_len + i, err_off + i);
-            LAUNCH_TRY();
-            continue;
-        }
+        if (n == 0) continue;  // verdict (0, -1) comes from the init and final passes
         int rc = enqueue_decode(src + h_in_off[i], n, dst + h_out_off[i], fl & 7,
-                                (unsigned long long *)(err_off + i), (unsigned int *)(out_len + i),
-                                out_len + i, err_off + i, 0, s);
+                                (unsigned long long *)(err_off + i), out_len + i, s);
         if (rc) return rc;
     }
+    hipLaunchKernelGGL(k_dec_batch_final, fb, 256, 0, s, N, out_len, err_off);
+    LAUNCH_TRY();
     return B64_OK;
 }
 

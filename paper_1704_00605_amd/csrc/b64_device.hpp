@@ -38,7 +38,9 @@ constexpr Tables make_tables()
 }
 
 constexpr uint8_t INVALID = 0x80;
-constexpr unsigned long long NO_ERR = ~0ull;
+// "No error yet" value of an error slot; real offsets are smaller (unsigned
+// atomicMin keeps the smallest).
+constexpr unsigned long long ERR_NONE = 0x7fffffffffffffffull;
 
 // Mode bits (per call or per message).
 constexpr int M_URL = 1;

@@ -1,0 +1,263 @@
+"""GPU parity of the batched codec (persistent kernels over a packed offsets
+table) and of the per-message baseline, against the oracle, per message:
+output bytes, out_len and error offset relative to the message start."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1704_00605_amd import codec, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+E, D = codec.DIR_ENCODE, codec.DIR_DECODE
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def packed(lens, seed, base=0):
+    rng = np.random.default_rng(seed)
+    lens = np.asarray(lens, dtype=np.int64)
+    off = np.zeros(lens.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    off += base
+    data = rng.integers(0, 256, int(off[-1]) + 7, dtype=np.uint8)
+    return data, off
+
+
+def check_encode(data, off, flags=None, tune=None):
+    want, want_off, want_len = oracle.encode_batch(data, off - off[0] if off[0] else off,
+                                                   flags) if off[0] == 0 else (None, None, None)
+    if off[0] != 0:
+        # messages start at in_off[0] > 0: the oracle sees the same bytes
+        want, want_off, want_len = oracle.encode_batch(data[off[0]:], off - off[0], flags)
+    fl = None if flags is None else dev(flags)
+    dst, out_off, out_len = codec.encode_batch(dev(data), dev(off), flags=fl, tune=tune)
+    assert np.array_equal(host(out_off), want_off)
+    assert np.array_equal(host(out_len), want_len)
+    assert np.array_equal(host(dst)[: want.size], want)
+    return dst, out_off
+
+
+def check_decode(text, toff, flags=None, tune=None):
+    want, want_off, want_len, want_err = oracle.decode_batch(text, toff, flags)
+    fl = None if flags is None else dev(flags)
+    dst, out_off, out_len, err = codec.decode_batch(dev(text), dev(toff), flags=fl, tune=tune)
+    assert np.array_equal(host(out_off), want_off)
+    gl, ge = host(out_len), host(err)
+    bad = np.nonzero((gl != want_len) | (ge != want_err))[0]
+    assert bad.size == 0, f"{bad.size} messages differ, first {bad[:5]}: got {gl[bad[:5]]},{ge[bad[:5]]} want {want_len[bad[:5]]},{want_err[bad[:5]]}"
+    # decoded bytes of valid messages; the rest of each capacity slot (and
+    # the whole slot of an invalid message) is unspecified
+    mask = decoded_mask(want_off, want_len, want.size)
+    assert np.array_equal(host(dst)[: want.size][mask], want[mask])
+    return gl, ge
+
+
+def decoded_mask(out_off, out_len, size):
+    mask = np.zeros(size, dtype=bool)
+    for i in np.nonzero(out_len > 0)[0]:
+        mask[out_off[i]:out_off[i] + out_len[i]] = True
+    return mask
+
+
+def encode_text(data, off, flags=None):
+    t, toff, _ = oracle.encode_batch(data[off[0]:], off - off[0], flags)
+    return t, toff
+
+
+@pytest.mark.parametrize("lens", [
+    [0], [1], [5], [12], [13], [0, 0, 0], [3] * 1000, list(range(0, 300)),
+    [1 << 20], [0, 1 << 20, 0, 7], [64 * 12 * 3 + 1] * 5,
+])
+def test_encode_batch_shapes(lens):
+    data, off = packed(lens, len(lens))
+    check_encode(data, off)
+
+
+def test_encode_batch_random_mix_with_alphabets():
+    rng = np.random.default_rng(1)
+    for trial in range(6):
+        N = int(rng.integers(1, 3000))
+        lens = np.where(rng.uniform(size=N) < 0.05, rng.integers(5000, 300_000, N), rng.integers(0, 200, N))
+        data, off = packed(lens, trial)
+        flags = rng.integers(0, 2, N).astype(np.uint8)
+        check_encode(data, off, flags)
+
+
+def test_encode_batch_unaligned_starts():
+    # in_off[0] > 0 and odd offsets put every message at a different alignment
+    data, off = packed(np.random.default_rng(3).integers(0, 5000, 500), 3, base=3)
+    check_encode(data, off)
+
+
+@pytest.mark.parametrize("tune", [dict(block=64, units_per_lane=1, grid=1), dict(block=1024, units_per_lane=8, grid=3),
+                                  dict(block=256, units_per_lane=4, grid=4096), dict(block=128, units_per_lane=2, grid=17)])
+def test_batch_launch_shapes_agree(tune):
+    rng = np.random.default_rng(9)
+    lens = np.concatenate([rng.integers(0, 100, 2000), rng.integers(10_000, 100_000, 30)])
+    rng.shuffle(lens)
+    data, off = packed(lens, 9)
+    check_encode(data, off, tune=tune)
+    text, toff = encode_text(data, off)
+    check_decode(text, toff, tune=tune)
+
+
+def test_decode_batch_valid_and_corrupted():
+    rng = np.random.default_rng(2)
+    for trial in range(5):
+        N = int(rng.integers(1, 4000))
+        lens = np.where(rng.uniform(size=N) < 0.03, rng.integers(4000, 200_000, N), rng.integers(0, 300, N))
+        data, off = packed(lens, 100 + trial)
+        flags = rng.integers(0, 2, N).astype(np.uint8)
+        text, toff = encode_text(data, off, flags)
+        k = max(1, N // 20)
+        ids = rng.choice(N, size=k, replace=False)
+        workloads.corrupt_text(text, toff, ids, rng.uniform(size=k), rng.integers(0, 192, k), flags)
+        gl, ge = check_decode(text, toff, flags)
+        assert (ge >= 0).sum() >= 1
+
+
+def test_decode_batch_garbage_lengths_and_padding():
+    """Messages of every length 0..70 made of random symbols, '=' and other
+    bytes: exercises length errors, misplaced padding and tails."""
+    rng = np.random.default_rng(4)
+    pool = np.frombuffer(b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/==-_*\n", np.uint8)
+    msgs = []
+    for L in range(0, 71):
+        for rep in range(8):
+            m = pool[rng.integers(0, 64, L)].copy()  # symbols only
+            if rep % 4 == 1 and L >= 2:
+                m[-1] = ord("=")
+            if rep % 4 == 2 and L >= 2:
+                m[-2:] = ord("=")
+            if rep % 4 == 3 and L:
+                m[rng.integers(0, L)] = pool[rng.integers(0, pool.size)]
+            msgs.append(m)
+    lens = np.array([m.size for m in msgs], dtype=np.int64)
+    toff = np.zeros(lens.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=toff[1:])
+    text = np.concatenate(msgs)
+    check_decode(text, toff)
+    check_decode(text, toff, np.ones(lens.size, np.uint8))
+
+
+def test_batch_matches_single_and_each():
+    rng = np.random.default_rng(6)
+    lens = rng.integers(0, 3000, 300)
+    data, off = packed(lens, 6)
+    flags = rng.integers(0, 2, lens.size).astype(np.uint8)
+    dst, out_off = check_encode(data, off, flags)
+    # per-message launches give the same bytes
+    dst2 = torch.zeros_like(dst)
+    ol2 = torch.zeros(lens.size, dtype=torch.int64, device=DEV)
+    codec.encode_each(dev(data), off, host(out_off), dst2, ol2, h_flags=flags)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, dst2)
+    assert np.array_equal(host(ol2), 4 * ((lens + 2) // 3))
+    text, toff = encode_text(data, off, flags)
+    for i in rng.choice(lens.size, 10, replace=False):
+        t = text[toff[i]:toff[i + 1]]
+        out, err = codec.decode(dev(t) if t.size else torch.empty(0, dtype=torch.uint8, device=DEV), int(flags[i]))
+        assert err == -1 and np.array_equal(host(out), data[off[i]:off[i + 1]])
+    k = 15
+    ids = rng.choice(lens.size, size=k, replace=False)
+    workloads.corrupt_text(text, toff, ids, rng.uniform(size=k), rng.integers(0, 192, k), flags)
+    gl, ge = check_decode(text, toff, flags)
+    dcap = 3 * (np.diff(toff) // 4)
+    doff = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(dcap, out=doff[1:])
+    ddst = torch.zeros(max(int(doff[-1]), 1), dtype=torch.uint8, device=DEV)
+    dl = torch.zeros(lens.size, dtype=torch.int64, device=DEV)
+    de = torch.zeros(lens.size, dtype=torch.int64, device=DEV)
+    codec.decode_each(dev(text), toff, doff, ddst, dl, de, h_flags=flags)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(dl), gl) and np.array_equal(host(de), ge)
+
+
+def test_per_message_modes_in_batch():
+    """Per-message flags: URL alphabet, unpadded, strict."""
+    rng = np.random.default_rng(12)
+    N = 600
+    lens = rng.integers(0, 80, N)
+    data, off = packed(lens, 12)
+    flags = rng.choice([0, 1, 4, 5], N).astype(np.uint8)  # std/url x padded/unpadded
+    dst, out_off, out_len = codec.encode_batch(dev(data), dev(off), flags=dev(flags))
+    d, oo, ol = host(dst), host(out_off), host(out_len)
+    texts = []
+    for i in range(N):
+        x = data[off[i]:off[i + 1]]
+        w = oracle.encode_nopad(x, flags[i] & 1) if flags[i] & 4 else oracle.encode(x, flags[i] & 1)
+        assert ol[i] == w.size and np.array_equal(d[oo[i]:oo[i] + w.size], w), i
+        texts.append(w)
+    # decode them back; strict flag on the padded ones; some corrupted
+    dflags = np.where(flags & 4, flags, flags | 2).astype(np.uint8)
+    for i in rng.choice(N, 40, replace=False):
+        if texts[i].size:
+            t = texts[i].copy()
+            t[rng.integers(0, t.size)] = ord("*")
+            texts[i] = t
+    tl = np.array([t.size for t in texts], np.int64)
+    toff = np.zeros(N + 1, np.int64)
+    np.cumsum(tl, out=toff[1:])
+    text = np.concatenate(texts)
+    dst, out_off, out_len, err = codec.decode_batch(dev(text), dev(toff), flags=dev(dflags))
+    d, oo, ol, oe = host(dst), host(out_off), host(out_len), host(err)
+    for i in range(N):
+        t = texts[i]
+        if dflags[i] & 4:
+            w = oracle.decode_nopad(t, dflags[i] & 1)
+        else:
+            w = oracle.decode_strict(t, dflags[i] & 1)
+        assert (ol[i], oe[i]) == w[:2], (i, dflags[i], bytes(t))
+        if w[0] >= 0:
+            assert np.array_equal(d[oo[i]:oo[i] + w[0]], w[2])
+
+
+def test_config3_uneven_100k_messages():
+    w = workloads.uneven()
+    data, off = w["payload"], w["in_off"]
+    assert off.size == 100_001
+    lens = np.diff(off)
+    assert set(np.unique(lens % 3)) == {0, 1, 2}
+    check_encode(data, off)
+    text, toff = encode_text(data, off)
+    applied = workloads.corrupt_text(text, toff, w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"])
+    assert len(applied) == 1000
+    gl, ge = check_decode(text, toff)
+    for m_id, pos, b in applied:
+        assert ge[m_id] >= 0 and ge[m_id] <= pos
+
+
+def test_config4_shaped_heavy_mix_scaled():
+    """The heavy-tailed mix with per-message alphabets at reduced count
+    (large messages 1-4 MiB) so the oracle finishes in seconds."""
+    w = workloads.heavy_mix(count=1024, n_large=102, large=(1 << 20, 4 << 20), seed=3)
+    data, off, flags = w["payload"], w["in_off"], w["flags"]
+    check_encode(data, off, flags)
+    text, toff = encode_text(data, off, flags)
+    workloads.corrupt_text(text, toff, w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"], flags)
+    check_decode(text, toff, flags)
+
+
+def test_out_offsets_scan_sizes():
+    rng = np.random.default_rng(7)
+    for N in [0, 1, 2, 1023, 1024, 1025, 5000, 100_000]:
+        lens = rng.integers(0, 100, N).astype(np.int64)
+        off = np.zeros(N + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        fl = rng.choice([0, 4], N).astype(np.uint8)
+        e = host(codec.batch_out_offsets(E, dev(off)))
+        d = host(codec.batch_out_offsets(D, dev(off), flags=dev(fl) if N else None))
+        we = np.zeros(N + 1, np.int64)
+        np.cumsum(4 * ((lens + 2) // 3), out=we[1:])
+        cap = 3 * (lens // 4) + np.where(fl & 4, np.maximum(lens % 4 - 1, 0), 0)
+        wd = np.zeros(N + 1, np.int64)
+        np.cumsum(cap, out=wd[1:])
+        assert np.array_equal(e, we) and np.array_equal(d, wd)

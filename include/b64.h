@@ -32,7 +32,9 @@
  *       B64_INVALID_INPUT (-1) decode found an invalid character or length;
  *       B64_BAD_ARG (-2) null pointer with n > 0, n < 0, bad alphabet, too
  *       small workspace, bad tuning values;
- *       B64_HIP_ERROR (-3) a HIP runtime call failed.
+ *       B64_HIP_ERROR (-3) a HIP runtime call failed;
+ *       B64_POOL_FULL (-4) a pool allocation found no free block (pools);
+ *       B64_TIMEOUT (-5) the serving loop hit its time limit.
  *     b64_last_error() describes the most recent failure on this thread.
  *   - No entry point allocates device memory during the call except the
  *     synchronous b64_decode / b64_decode_ex, which on first use on a thread
@@ -52,6 +54,8 @@ extern "C" {
 #define B64_INVALID_INPUT (-1)
 #define B64_BAD_ARG (-2)
 #define B64_HIP_ERROR (-3)
+#define B64_POOL_FULL (-4)
+#define B64_TIMEOUT (-5)
 
 /* Alphabets (Section 2): Table 1, or base64url. */
 #define B64_ALPHABET_STD 0
@@ -165,6 +169,103 @@ int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8
                      const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
                      int64_t *err_off, void *workspace, int64_t workspace_bytes,
                      const b64_tune *tune, void *stream);
+
+/* Gather forms: message i is src[in_begin[i], in_begin[i] + in_len[i]) with
+ * in_begin / in_len DEVICE arrays of N entries (messages may overlap, be in
+ * any order and at any alignment); everything else as in the packed forms. */
+int b64_encode_batch_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len,
+                            int64_t N, uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                            int64_t *out_len, void *workspace, int64_t workspace_bytes,
+                            const b64_tune *tune, void *stream);
+int b64_decode_batch_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len,
+                            int64_t N, uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                            int64_t *out_len, int64_t *err_off, void *workspace,
+                            int64_t workspace_bytes, const b64_tune *tune, void *stream);
+
+/* ------------------------------------------------------------------------
+ * HIP graphs of batched calls: the planning and codec kernels of one
+ * b64_encode_batch / b64_decode_batch (dir) are captured once and replayed
+ * with a single graph launch. Arguments as for the packed batched calls; the
+ * graph keeps the pointers, so the buffers must outlive it. update re-captures
+ * with new pointers / N and updates the instantiated graph in place (falling
+ * back to a fresh instantiation when the kernel topology changed). The graph
+ * contains kernel nodes only (no memset nodes).
+ * ------------------------------------------------------------------------ */
+typedef struct b64_graph b64_graph;
+int b64_graph_create_batch(int dir, const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                           const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                           int64_t *err_off, void *workspace, int64_t workspace_bytes,
+                           const b64_tune *tune, b64_graph **out);
+int b64_graph_update_batch(b64_graph *g, const uint8_t *src, const int64_t *in_off, int64_t N,
+                           uint8_t *dst, const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                           int64_t *err_off, void *workspace, int64_t workspace_bytes,
+                           const b64_tune *tune);
+int b64_graph_launch(b64_graph *g, void *stream);
+int b64_graph_destroy(b64_graph *g);
+
+/* ------------------------------------------------------------------------
+ * Device memory pool (buddy allocator). The pool is host-side bookkeeping of
+ * offsets in [0, capacity); the caller maps them onto its own device
+ * allocation. Blocks are powers of two times min_block (a power of two,
+ * default 256) and aligned to their size. b64_pool_alloc never blocks: it
+ * returns B64_POOL_FULL when no block is free, which is what drives
+ * admission in the serving loop. Thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct b64_pool b64_pool;
+int b64_pool_create(int64_t capacity, int64_t min_block, b64_pool **out);
+int b64_pool_alloc(b64_pool *p, int64_t bytes, int64_t *offset);
+int b64_pool_free(b64_pool *p, int64_t offset);
+int64_t b64_pool_free_bytes(b64_pool *p);
+int64_t b64_pool_peak_bytes(b64_pool *p);
+int b64_pool_destroy(b64_pool *p);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching serving loop. Request r arrives at t_arrival[r] *
+ * time_scale seconds after the call starts (t_arrival non-decreasing); op[r]
+ * is B64_DIR_ENCODE or B64_DIR_DECODE; its input is
+ * enc_src / dec_src [in_begin[r], in_begin[r] + in_len[r]) (device banks of
+ * enc_src_bytes / dec_src_bytes bytes; a request outside its bank, an unknown
+ * op or decreasing arrival times make the call return B64_BAD_ARG before any
+ * work) and flags[r] (nullable) its per-message flags. pool_base must hold
+ * the pool's capacity. Arrived requests are admitted in
+ * order when the pool can hold their output (4 * ceil(n / 3) bytes to
+ * encode, 3 * floor(n / 4) + 2 to decode); otherwise admission waits for
+ * completed requests to release memory. Admitted requests of one direction
+ * are launched together (gather form of the batched kernels, host-built
+ * plan) on one of `streams` streams when max_batch are ready, when the
+ * oldest has waited tick_us, or when admission is blocked; batches on
+ * different streams overlap on the GPU. Completion is detected by polling
+ * one event per batch. Outputs: t_done[r] (seconds since the call started,
+ * host clock), out_off[r] (pool offset of the output), out_len[r] and
+ * err_off[r] (the single-buffer verdict). With capture != 0 outputs are not
+ * released (so callers can read them afterwards). Blocks the calling thread
+ * until every request completed, the pool cannot ever admit the next
+ * request (B64_POOL_FULL) or max_seconds passed (B64_TIMEOUT); in-flight
+ * work is always drained before returning.
+ * ------------------------------------------------------------------------ */
+typedef struct b64_server_cfg {
+    int32_t max_batch;      /* requests per launch and direction */
+    int32_t tick_us;        /* longest wait of an admitted request before its batch launches */
+    int32_t streams;        /* batches in flight (1..16) */
+    int32_t capture;        /* keep outputs allocated after completion */
+    int32_t idle_sleep_us;  /* sleep when nothing is in flight or ready (0 = spin) */
+    int32_t block, units_per_lane, grid;  /* batched kernel launch shape (0 = default) */
+    double time_scale;      /* arrival time multiplier (1 = real time, 0 = all at once) */
+    double max_seconds;     /* wall-clock limit of the call (0 = 600) */
+} b64_server_cfg;
+
+typedef struct b64_server_stats {
+    int64_t completed, batches, launched_requests, pool_waits, max_inflight_batches;
+    int64_t bytes_in, bytes_out, peak_pool_bytes;
+    double wall_s;
+} b64_server_stats;
+
+int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const double *t_arrival,
+                   const uint8_t *op, const int64_t *in_begin, const int64_t *in_len,
+                   const uint8_t *flags, const uint8_t *enc_src, int64_t enc_src_bytes,
+                   const uint8_t *dec_src, int64_t dec_src_bytes, b64_pool *pool,
+                   uint8_t *pool_base, double *t_done, int64_t *out_off, int64_t *out_len,
+                   int64_t *err_off, b64_server_stats *stats);
 
 /* Plain per-message form of the batched calls (the baseline the batched
  * kernels are measured against): one single-buffer launch per message, all on

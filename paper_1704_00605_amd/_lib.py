@@ -13,6 +13,8 @@ OK = 0
 INVALID_INPUT = -1
 BAD_ARG = -2
 HIP_ERROR = -3
+POOL_FULL = -4
+TIMEOUT = -5
 
 ALPHABET_STD = 0
 ALPHABET_URL = 1
@@ -34,6 +36,26 @@ class Tune(ctypes.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class ServerCfg(ctypes.Structure):
+    """``b64_server_cfg``."""
+    _fields_ = [("max_batch", ctypes.c_int32), ("tick_us", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("capture", ctypes.c_int32), ("idle_sleep_us", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("units_per_lane", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("time_scale", ctypes.c_double), ("max_seconds", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    """``b64_server_stats``."""
+    _fields_ = [("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("launched_requests", ctypes.c_int64), ("pool_waits", ctypes.c_int64),
+                ("max_inflight_batches", ctypes.c_int64), ("bytes_in", ctypes.c_int64),
+                ("bytes_out", ctypes.c_int64), ("peak_pool_bytes", ctypes.c_int64),
+                ("wall_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _i64, _i32, _p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -58,6 +80,21 @@ SIGNATURES = {
     "b64_encode_each": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p]),
     "b64_decode_each": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p]),
     "b64_set_single_tune": (_i32, [_i32, _ptune]),
+    "b64_encode_batch_gather": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _i64, _ptune, _p]),
+    "b64_decode_batch_gather": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _ptune, _p]),
+    "b64_graph_create_batch": (_i32, [_i32, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _ptune,
+                                      ctypes.POINTER(_p)]),
+    "b64_graph_update_batch": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _ptune]),
+    "b64_graph_launch": (_i32, [_p, _p]),
+    "b64_graph_destroy": (_i32, [_p]),
+    "b64_pool_create": (_i32, [_i64, _i64, ctypes.POINTER(_p)]),
+    "b64_pool_alloc": (_i32, [_p, _i64, _pi64]),
+    "b64_pool_free": (_i32, [_p, _i64]),
+    "b64_pool_free_bytes": (_i64, [_p]),
+    "b64_pool_peak_bytes": (_i64, [_p]),
+    "b64_pool_destroy": (_i32, [_p]),
+    "b64_server_run": (_i32, [ctypes.POINTER(ServerCfg), _i64, _p, _p, _p, _p, _p, _p, _i64, _p, _i64,
+                              _p, _p, _p, _p, _p, _p, ctypes.POINTER(ServerStats)]),
     "b64_last_error": (ctypes.c_char_p, []),
     "b64_device_cus": (_i32, []),
 }

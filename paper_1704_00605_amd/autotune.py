@@ -1,0 +1,135 @@
+"""Autotuner for the persistent batched kernels.
+
+Searches the launch shape (threads per workgroup, units per lane, workgroups
+in the persistent grid) of ``b64_encode_batch`` / ``b64_decode_batch`` on the
+actual batch, timing each candidate with HIP events, and caches the winner in
+a JSON file keyed by device, architecture, direction and a coarse signature
+of the batch (message count, total bytes and the log2 histogram of message
+lengths). The tile of one workgroup step is ``block * units_per_lane``
+units of 12 bytes (encode) or 16 characters (decode); how many messages share
+a workgroup step follows from it and the size histogram and is reported as
+``msgs_per_wg_step``.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import codec
+
+BLOCKS = (128, 256, 512, 1024)
+UNITS = (1, 2, 4, 8)
+GRID_PER_CU = (2, 4, 8, 16)
+
+
+def cache_path():
+    p = os.environ.get("B64HIP_TUNE_CACHE")
+    if p:
+        return p
+    home = os.path.expanduser("~")
+    d = os.path.join(home, ".cache", "b64hip")
+    try:
+        os.makedirs(d, exist_ok=True)
+        return os.path.join(d, "tune.json")
+    except OSError:
+        return os.path.join("/tmp", "b64hip_tune.json")
+
+
+def signature(in_off_host):
+    lens = np.diff(np.asarray(in_off_host, dtype=np.int64))
+    N = lens.size
+    hist = np.bincount(np.minimum(np.log2(np.maximum(lens, 1)).astype(np.int64), 40), minlength=41)
+    frac = np.round(hist / max(N, 1), 2)
+    return {"N_log2": int(np.log2(max(N, 1))), "bytes_log2": int(np.log2(max(int(lens.sum()), 1))),
+            "hist": [float(x) for x in frac]}
+
+
+def _key(direction, sig):
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "unknown")
+    return f"{props.name}|{arch}|dir{direction}|{json.dumps(sig, sort_keys=True)}"
+
+
+def load_cache():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(c):
+    p = cache_path()
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1)
+    os.replace(tmp, p)
+
+
+def candidates(cus):
+    return [dict(block=b, units_per_lane=u, grid=g * cus) for b in BLOCKS for u in UNITS for g in GRID_PER_CU]
+
+
+def time_call(fn, reps):
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]))
+
+
+def tune(direction, src, in_off, flags=None, in_off_host=None, reps=3, cands=None, use_cache=True,
+         verbose=False):
+    """Best launch shape for this batch; returns (tune dict, report)."""
+    if in_off_host is None:
+        in_off_host = in_off.cpu().numpy()
+    sig = signature(in_off_host)
+    key = _key(direction, sig)
+    cache = load_cache() if use_cache else {}
+    if use_cache and key in cache:
+        return cache[key]["tune"], cache[key]
+    N = in_off.numel() - 1
+    cus = codec.lib().b64_device_cus()
+    out_off = codec.batch_out_offsets(direction, in_off, flags)
+    total = int(out_off[-1].item())
+    dst = torch.empty(max(total, 1), dtype=torch.uint8, device=src.device)
+    out_len = torch.empty(max(N, 1), dtype=torch.int64, device=src.device)
+    err = torch.empty(max(N, 1), dtype=torch.int64, device=src.device)
+    ws = codec.Workspace()
+    results = []
+    t0 = time.perf_counter()
+    for c in cands or candidates(cus):
+        if direction == codec.DIR_ENCODE:
+            fn = lambda: codec.encode_batch(src, in_off, out_off, flags, dst, out_len, tune=c, workspace=ws)
+        else:
+            fn = lambda: codec.decode_batch(src, in_off, out_off, flags, dst, out_len, err, tune=c, workspace=ws)
+        ms = time_call(fn, reps)
+        results.append((ms, c))
+        if verbose:
+            print(f"  {c} {ms:.4f} ms", flush=True)
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    units = in_off_host[-1] - in_off_host[0]
+    unit = 12 if direction == codec.DIR_ENCODE else 16
+    tile_units = best["block"] * best["units_per_lane"]
+    msg_units = np.maximum(-(-np.diff(np.asarray(in_off_host)) // unit), 1)
+    entry = {
+        "tune": best, "ms": round(best_ms, 4), "worst_ms": round(results[-1][0], 4),
+        "default_ms": None, "candidates": len(results), "tuning_s": round(time.perf_counter() - t0, 2),
+        "msgs_per_wg_step": round(float(tile_units / msg_units.mean()), 2),
+        "bytes": int(units), "signature": sig,
+    }
+    for ms, c in results:
+        if c["block"] == 256 and c["units_per_lane"] == 2 and c["grid"] == 8 * cus:
+            entry["default_ms"] = round(ms, 4)
+    if use_cache:
+        cache[key] = entry
+        save_cache(cache)
+    return best, entry

@@ -15,7 +15,7 @@ from ._lib import (ALPHABET_STD, ALPHABET_URL, DIR_DECODE, DIR_ENCODE, FLAG_NOPA
 
 __all__ = [
     "encode", "decode", "decode_async", "encoded_len", "decoded_max", "batch_out_offsets",
-    "encode_batch", "decode_batch", "encode_each", "decode_each", "workspace_bytes", "set_single_tune",
+    "encode_batch", "decode_batch", "encode_batch_gather", "decode_batch_gather", "encode_each", "decode_each", "workspace_bytes", "set_single_tune",
     "ALPHABET_STD", "ALPHABET_URL", "MODE_STRICT", "MODE_NOPAD", "FLAG_URL", "FLAG_STRICT",
     "FLAG_NOPAD", "DIR_ENCODE", "DIR_DECODE", "Tune", "B64Error",
 ]
@@ -162,7 +162,7 @@ def _ws(ws, N, device):
 
 
 def encode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, tune=None,
-                 workspace=None, stream=None, total_out=None):
+                 workspace=None, stream=None, total_out=None, validate=True):
     """Encode N packed messages in one persistent launch.
 
     Returns ``(dst, out_off, out_len)``. ``total_out`` (host int, the last
@@ -178,6 +178,8 @@ def encode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
         dst = torch.empty(max(tot, 1), dtype=torch.uint8, device=dev)
     if out_len is None:
         out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    if validate:
+        _validate_packed(src, in_off, out_off, dst, DIR_ENCODE, flags)
     ws = _ws(workspace, N, dev)
     r = lib().b64_encode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off), _ptr(flags),
                                _ptr(out_len), _ptr(ws), ws.numel(), _tune(tune), _stream(stream))
@@ -186,7 +188,7 @@ def encode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
 
 
 def decode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, err_off=None,
-                 tune=None, workspace=None, stream=None, total_out=None):
+                 tune=None, workspace=None, stream=None, total_out=None, validate=True):
     """Decode N packed messages in one persistent launch.
 
     Returns ``(dst, out_off, out_len, err_off)``; per message out_len is the
@@ -204,11 +206,111 @@ def decode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
         out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
     if err_off is None:
         err_off = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    if validate:
+        _validate_packed(src, in_off, out_off, dst, DIR_DECODE, flags)
     ws = _ws(workspace, N, dev)
     r = lib().b64_decode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off), _ptr(flags),
                                _ptr(out_len), _ptr(err_off), _ptr(ws), ws.numel(), _tune(tune),
                                _stream(stream))
     check(r, "b64_decode_batch")
+    return dst, out_off, out_len[:N], err_off[:N]
+
+
+def _validate_packed(src, in_off, out_off, dst, direction, flags=None):
+    """Host-side check of a packed batch before launch (reads the offsets
+    back): offsets non-decreasing and inside src, output slots inside dst."""
+    import numpy as np
+    o = in_off.cpu().numpy()
+    if o.size < 1 or np.any(np.diff(o) < 0) or o[0] < 0 or o[-1] > src.numel():
+        raise ValueError("in_off must be non-decreasing and inside src")
+    lens = np.diff(o)
+    oo = out_off.cpu().numpy()
+    _check_slots(oo[: lens.size], lens, direction, flags, dst)
+
+
+def _check_slots(oo, lens, direction, flags, dst):
+    import numpy as np
+    fl = np.zeros(lens.size, np.uint8) if flags is None else flags.cpu().numpy()
+    if direction == DIR_ENCODE:
+        cap = 4 * ((lens + 2) // 3)
+    else:
+        cap = 3 * (lens // 4) + np.where(fl & FLAG_NOPAD, np.maximum(lens % 4 - 1, 0), 0)
+    if lens.size and (np.any(oo < 0) or np.any(oo + cap > dst.numel())):
+        raise ValueError("output slots fall outside dst")
+
+
+def _validate_gather(src, in_begin, in_len, out_off, dst, direction, flags=None):
+    import numpy as np
+    b = in_begin.cpu().numpy()
+    n = in_len.cpu().numpy()
+    if b.size != n.size or np.any(n < 0) or np.any(b < 0) or np.any(b + n > src.numel()):
+        raise ValueError("every message span must lie inside src")
+    _check_slots(out_off.cpu().numpy(), n, direction, flags, dst)
+
+
+def _gather_out_off(in_len, direction, flags, device):
+    import numpy as np
+    n = in_len.cpu().numpy()
+    fl = np.zeros(n.size, np.uint8) if flags is None else flags.cpu().numpy()
+    if direction == DIR_ENCODE:
+        cap = 4 * ((n + 2) // 3)
+    else:
+        cap = 3 * (n // 4) + np.where(fl & FLAG_NOPAD, np.maximum(n % 4 - 1, 0), 0)
+    oo = np.zeros(n.size, np.int64)
+    if n.size > 1:
+        oo[1:] = np.cumsum(cap)[:-1]
+    return torch.from_numpy(oo).to(device), int(cap.sum())
+
+
+def encode_batch_gather(src, in_begin, in_len, out_off=None, flags=None, dst=None, out_len=None,
+                        tune=None, workspace=None, stream=None, validate=True):
+    """Encode messages src[in_begin[i], in_begin[i] + in_len[i]) (device int64
+    arrays) in one persistent launch. Returns (dst, out_off, out_len)."""
+    src = _dev_u8(src, "src")
+    in_begin = _i64_dev(in_begin, "in_begin")
+    in_len = _i64_dev(in_len, "in_len")
+    N = in_begin.numel()
+    dev = src.device
+    if out_off is None:
+        out_off, total = _gather_out_off(in_len, DIR_ENCODE, flags, dev)
+        if dst is None:
+            dst = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    if out_len is None:
+        out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    if validate:
+        _validate_gather(src, in_begin, in_len, out_off, dst, DIR_ENCODE, flags)
+    ws = _ws(workspace, N, dev)
+    r = lib().b64_encode_batch_gather(_ptr(src), _ptr(in_begin), _ptr(in_len), N, _ptr(dst), _ptr(out_off),
+                                      _ptr(flags), _ptr(out_len), _ptr(ws), ws.numel(), _tune(tune),
+                                      _stream(stream))
+    check(r, "b64_encode_batch_gather")
+    return dst, out_off, out_len[:N]
+
+
+def decode_batch_gather(src, in_begin, in_len, out_off=None, flags=None, dst=None, out_len=None,
+                        err_off=None, tune=None, workspace=None, stream=None, validate=True):
+    """Decode messages src[in_begin[i], in_begin[i] + in_len[i]) in one
+    persistent launch. Returns (dst, out_off, out_len, err_off)."""
+    src = _dev_u8(src, "src")
+    in_begin = _i64_dev(in_begin, "in_begin")
+    in_len = _i64_dev(in_len, "in_len")
+    N = in_begin.numel()
+    dev = src.device
+    if out_off is None:
+        out_off, total = _gather_out_off(in_len, DIR_DECODE, flags, dev)
+        if dst is None:
+            dst = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    if out_len is None:
+        out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    if err_off is None:
+        err_off = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    if validate:
+        _validate_gather(src, in_begin, in_len, out_off, dst, DIR_DECODE, flags)
+    ws = _ws(workspace, N, dev)
+    r = lib().b64_decode_batch_gather(_ptr(src), _ptr(in_begin), _ptr(in_len), N, _ptr(dst), _ptr(out_off),
+                                      _ptr(flags), _ptr(out_len), _ptr(err_off), _ptr(ws), ws.numel(),
+                                      _tune(tune), _stream(stream))
+    check(r, "b64_decode_batch_gather")
     return dst, out_off, out_len[:N], err_off[:N]
 
 

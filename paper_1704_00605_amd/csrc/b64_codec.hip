@@ -275,6 +275,16 @@ __device__ __forceinline__ int64_t dec_cap_of(int64_t len, int nopad)
     return 3 * (len / 4) + ((nopad && (len & 3) >= 2) ? (len & 3) - 1 : 0);
 }
 
+// Where the messages of a batch are. Packed form: message i is
+// [begin[i], begin[i+1]) (len == nullptr, begin has N + 1 entries). Gather
+// form: message i is [begin[i], begin[i] + len[i]).
+struct Msgs {
+    const int64_t *begin;
+    const int64_t *len;
+    __device__ __forceinline__ int64_t b(int64_t i) const { return begin[i]; }
+    __device__ __forceinline__ int64_t n(int64_t i) const { return len ? len[i] : begin[i + 1] - begin[i]; }
+};
+
 // Block-wide exclusive scan of one int64 per thread (blockDim.x <= 1024).
 __device__ int64_t block_exclusive_scan(int64_t v)
 {
@@ -311,14 +321,14 @@ __device__ int64_t block_sum(int64_t v)
 
 // Per-chunk totals of work units.
 template <int DIR>
-__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_reduce(const int64_t *__restrict__ in_off,
-                                                            int64_t N, int64_t *__restrict__ partial)
+__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_reduce(Msgs msgs, int64_t N,
+                                                            int64_t *__restrict__ partial)
 {
     const int64_t i0 = (int64_t)blockIdx.x * PLAN_CHUNK + threadIdx.x * PLAN_PER_THREAD;
     int64_t s = 0;
     for (int k = 0; k < PLAN_PER_THREAD; k++) {
         const int64_t i = i0 + k;
-        if (i < N) s += units_of(DIR, in_off[i + 1] - in_off[i]);
+        if (i < N) s += units_of(DIR, msgs.n(i));
     }
     s = block_sum(s);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -329,7 +339,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_reduce(const int64_t *__res
 // decode out_len = 0 and err_off = ERR_NONE (the atomicMin sentinel).
 template <int DIR>
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
-    const int64_t *__restrict__ in_off, int64_t N, const uint8_t *__restrict__ flags,
+    Msgs msgs, int64_t N, const uint8_t *__restrict__ flags,
     const int64_t *__restrict__ partial, int64_t *__restrict__ unit_off,
     int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
 {
@@ -343,7 +353,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
         const int64_t i = i0 + k;
         u[k] = 0;
         if (i < N) {
-            const int64_t len = in_off[i + 1] - in_off[i];
+            const int64_t len = msgs.n(i);
             const int fl = flags ? flags[i] : 0;
             u[k] = units_of(DIR, len);
             if (DIR == B64_DIR_ENCODE) {
@@ -462,7 +472,7 @@ __device__ __forceinline__ void wave_share(int64_t U, int64_t &g0, int64_t &g1)
 
 template <int UPL>
 __global__ __launch_bounds__(1024) void k_enc_batch(
-    const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t N,
+    const uint8_t *__restrict__ src, Msgs msgs, int64_t N,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
     const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off)
 {
@@ -485,8 +495,8 @@ __global__ __launch_bounds__(1024) void k_enc_batch(
             if (g + k < g1) {
                 r[k] = resolve_group(unit_off, N, U, (g + k) * 64, m);
                 if (r[k].valid) {
-                    const int64_t b = in_off[r[k].msg];
-                    const int64_t len = in_off[r[k].msg + 1] - b;
+                    const int64_t b = msgs.b(r[k].msg);
+                    const int64_t len = msgs.n(r[k].msg);
                     full[k] = 12 * r[k].j + 12 <= len;
                     if (full[k]) load12(src + b + 12 * r[k].j, w[k][0], w[k][1], w[k][2]);
                 }
@@ -504,8 +514,8 @@ __global__ __launch_bounds__(1024) void k_enc_batch(
                 enc_unit(w[k][0], w[k][1], w[k][2], tab, o[0], o[1], o[2], o[3]);
                 store_words<4>(q, o);
             } else {
-                const int64_t b = in_off[mm];
-                const int rem = (int)(in_off[mm + 1] - b - 12 * r[k].j);
+                const int64_t b = msgs.b(mm);
+                const int rem = (int)(msgs.n(mm) - 12 * r[k].j);
                 enc_tail(src + b + 12 * r[k].j, rem, q, tab, fl & M_NOPAD);
             }
         }
@@ -514,7 +524,7 @@ __global__ __launch_bounds__(1024) void k_enc_batch(
 
 template <int UPL>
 __global__ __launch_bounds__(1024) void k_dec_batch(
-    const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t N,
+    const uint8_t *__restrict__ src, Msgs msgs, int64_t N,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
     const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off,
     int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
@@ -538,8 +548,8 @@ __global__ __launch_bounds__(1024) void k_dec_batch(
             if (g + k < g1) {
                 r[k] = resolve_group(unit_off, N, U, (g + k) * 64, m);
                 if (r[k].valid) {
-                    const int64_t b = in_off[r[k].msg];
-                    const int64_t len = in_off[r[k].msg + 1] - b;
+                    const int64_t b = msgs.b(r[k].msg);
+                    const int64_t len = msgs.n(r[k].msg);
                     interior[k] = 16 * r[k].j + 16 < len;  // not the message's last unit
                     if (interior[k])
                         load16(src + b + 16 * r[k].j, w[k][0], w[k][1], w[k][2], w[k][3]);
@@ -553,7 +563,7 @@ __global__ __launch_bounds__(1024) void k_dec_batch(
             const int fl = flags ? flags[mm] : 0;
             const uint8_t *tab = (const uint8_t *)s_tab + 256 * (fl & M_URL);
             uint8_t *q = dst + out_off[mm] + 12 * r[k].j;
-            const int64_t b = in_off[mm];
+            const int64_t b = msgs.b(mm);
             if (interior[k]) {
                 uint32_t o[3];
                 const uint32_t bad = dec_unit(w[k][0], w[k][1], w[k][2], w[k][3], tab, o[0], o[1], o[2]);
@@ -563,7 +573,7 @@ __global__ __launch_bounds__(1024) void k_dec_batch(
                     atomicMin((unsigned long long *)&err_off[mm], (unsigned long long)pos);
                 }
             } else {
-                const int64_t len = in_off[mm + 1] - b;
+                const int64_t len = msgs.n(mm);
                 const int rem = (int)(len - 16 * r[k].j);
                 int nout;
                 const int idx = dec_tail(src + b + 16 * r[k].j, rem, len, q, tab, fl, &nout);
@@ -587,8 +597,8 @@ __global__ void k_dec_batch_final(int64_t N, int64_t *__restrict__ out_len, int6
 }
 
 // Exclusive scan of per-message output sizes by one workgroup.
-__global__ __launch_bounds__(1024) void k_out_offsets(int dir, const int64_t *__restrict__ in_off,
-                                                      int64_t N, const uint8_t *__restrict__ flags,
+__global__ __launch_bounds__(1024) void k_out_offsets(int dir, Msgs msgs, int64_t N,
+                                                      const uint8_t *__restrict__ flags,
                                                       int64_t *__restrict__ out_off)
 {
     const int64_t per = (N + blockDim.x - 1) / blockDim.x;
@@ -596,14 +606,14 @@ __global__ __launch_bounds__(1024) void k_out_offsets(int dir, const int64_t *__
     const int64_t i1 = min(N, i0 + per);
     int64_t s = 0;
     for (int64_t i = i0; i < i1; i++) {
-        const int64_t len = in_off[i + 1] - in_off[i];
+        const int64_t len = msgs.n(i);
         const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
         s += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_cap_of(len, nopad);
     }
     int64_t acc = block_exclusive_scan(s);
     for (int64_t i = i0; i < i1; i++) {
         out_off[i] = acc;
-        const int64_t len = in_off[i + 1] - in_off[i];
+        const int64_t len = msgs.n(i);
         const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
         acc += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_cap_of(len, nopad);
     }
@@ -919,7 +929,8 @@ int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *ou
 {
     if (dir != B64_DIR_ENCODE && dir != B64_DIR_DECODE) return fail(B64_BAD_ARG, "bad direction");
     if (N < 0 || !in_off || !out_off) return fail(B64_BAD_ARG, "bad offsets arguments");
-    hipLaunchKernelGGL(k_out_offsets, 1, 1024, 0, (hipStream_t)stream, dir, in_off, N, flags, out_off);
+    Msgs msgs{in_off, nullptr};
+    hipLaunchKernelGGL(k_out_offsets, 1, 1024, 0, (hipStream_t)stream, dir, msgs, N, flags, out_off);
     LAUNCH_TRY();
     return B64_OK;
 }
@@ -943,22 +954,114 @@ int batch_shape(const b64_tune *t, int *block, int *upl, int *grid)
 }
 
 template <int DIR>
-int plan(const int64_t *in_off, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes,
-         int64_t *out_len, int64_t *err_off, int64_t **unit_off, hipStream_t s)
+int plan(Msgs msgs, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes, int64_t *out_len,
+         int64_t *err_off, int64_t **unit_off, hipStream_t s)
 {
     if (ws_bytes < b64_batch_workspace_bytes(N) || !ws) return fail(B64_BAD_ARG, "workspace too small");
     const int64_t chunks = std::max<int64_t>(1, (N + PLAN_CHUNK - 1) / PLAN_CHUNK);
     *unit_off = (int64_t *)ws;
     int64_t *partial = (int64_t *)ws + (N + 1);
-    hipLaunchKernelGGL((k_plan_reduce<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, in_off, N, partial);
+    hipLaunchKernelGGL((k_plan_reduce<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, msgs, N, partial);
     LAUNCH_TRY();
-    hipLaunchKernelGGL((k_plan_scan<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, in_off, N, flags,
-                       partial, *unit_off, out_len, err_off);
+    hipLaunchKernelGGL((k_plan_scan<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, msgs, N, flags, partial,
+                       *unit_off, out_len, err_off);
     LAUNCH_TRY();
     return B64_OK;
 }
 
+int launch_enc_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
+                     const uint8_t *flags, const int64_t *unit_off, const b64_tune *tune, hipStream_t s)
+{
+    int block, upl, grid;
+    int rc = batch_shape(tune, &block, &upl, &grid);
+    if (rc) return rc;
+    switch (upl) {
+    case 1: hipLaunchKernelGGL((k_enc_batch<1>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
+    case 4: hipLaunchKernelGGL((k_enc_batch<4>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
+    case 8: hipLaunchKernelGGL((k_enc_batch<8>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
+    default: hipLaunchKernelGGL((k_enc_batch<2>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
+    }
+    LAUNCH_TRY();
+    return B64_OK;
+}
+
+int launch_dec_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
+                     const uint8_t *flags, const int64_t *unit_off, int64_t *out_len, int64_t *err_off,
+                     const b64_tune *tune, hipStream_t s)
+{
+    int block, upl, grid;
+    int rc = batch_shape(tune, &block, &upl, &grid);
+    if (rc) return rc;
+    switch (upl) {
+    case 1: hipLaunchKernelGGL((k_dec_batch<1>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
+    case 4: hipLaunchKernelGGL((k_dec_batch<4>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
+    case 8: hipLaunchKernelGGL((k_dec_batch<8>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
+    default: hipLaunchKernelGGL((k_dec_batch<2>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
+    }
+    LAUNCH_TRY();
+    const int fb = (int)std::min<int64_t>((N + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_dec_batch_final, fb, 256, 0, s, N, out_len, err_off);
+    LAUNCH_TRY();
+    return B64_OK;
+}
+
+int encode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
+                     const uint8_t *flags, int64_t *out_len, void *ws, int64_t ws_bytes,
+                     const b64_tune *tune, hipStream_t s)
+{
+    if (N < 0) return fail(B64_BAD_ARG, "negative N");
+    if (N == 0) return B64_OK;
+    if (!src || !msgs.begin || !dst || !out_off || !out_len) return fail(B64_BAD_ARG, "null argument");
+    int block, upl, grid;
+    int rc = batch_shape(tune, &block, &upl, &grid);
+    if (rc) return rc;
+    int64_t *unit_off;
+    rc = plan<B64_DIR_ENCODE>(msgs, N, flags, ws, ws_bytes, out_len, nullptr, &unit_off, s);
+    if (rc) return rc;
+    return launch_enc_batch(src, msgs, N, dst, out_off, flags, unit_off, tune, s);
+}
+
+int decode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
+                     const uint8_t *flags, int64_t *out_len, int64_t *err_off, void *ws,
+                     int64_t ws_bytes, const b64_tune *tune, hipStream_t s)
+{
+    if (N < 0) return fail(B64_BAD_ARG, "negative N");
+    if (N == 0) return B64_OK;
+    if (!src || !msgs.begin || !dst || !out_off || !out_len || !err_off) return fail(B64_BAD_ARG, "null argument");
+    int block, upl, grid;
+    int rc = batch_shape(tune, &block, &upl, &grid);
+    if (rc) return rc;
+    int64_t *unit_off;
+    rc = plan<B64_DIR_DECODE>(msgs, N, flags, ws, ws_bytes, out_len, err_off, &unit_off, s);
+    if (rc) return rc;
+    return launch_dec_batch(src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off, tune, s);
+}
+
 }  // namespace
+
+// Planned batch launches for the serving runtime: the caller supplies the
+// unit prefix (and, for decode, out_len = 0 / err_off = ERR_NONE) computed on
+// the host and uploaded together with the descriptors, so a serving batch is
+// one upload, one codec kernel and (decode) one verdict kernel.
+int b64i_encode_planned(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
+                        uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                        const int64_t *unit_off, const b64_tune *tune, hipStream_t s)
+{
+    if (N <= 0) return B64_OK;
+    return launch_enc_batch(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, unit_off, tune, s);
+}
+
+int b64i_decode_planned(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
+                        uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                        const int64_t *unit_off, int64_t *out_len, int64_t *err_off,
+                        const b64_tune *tune, hipStream_t s)
+{
+    if (N <= 0) return B64_OK;
+    return launch_dec_batch(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, unit_off, out_len,
+                            err_off, tune, s);
+}
+
+int b64i_fail(int code, const char *msg) { return fail(code, "%s", msg); }
 
 extern "C" {
 
@@ -966,24 +1069,8 @@ int b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8
                      const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
                      void *workspace, int64_t workspace_bytes, const b64_tune *tune, void *stream)
 {
-    if (N < 0) return fail(B64_BAD_ARG, "negative N");
-    if (N == 0) return B64_OK;
-    if (!src || !in_off || !dst || !out_off || !out_len) return fail(B64_BAD_ARG, "null argument");
-    int block, upl, grid;
-    int rc = batch_shape(tune, &block, &upl, &grid);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    int64_t *unit_off;
-    rc = plan<B64_DIR_ENCODE>(in_off, N, flags, workspace, workspace_bytes, out_len, nullptr, &unit_off, s);
-    if (rc) return rc;
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_enc_batch<1>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off); break;
-    case 4: hipLaunchKernelGGL((k_enc_batch<4>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off); break;
-    case 8: hipLaunchKernelGGL((k_enc_batch<8>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off); break;
-    default: hipLaunchKernelGGL((k_enc_batch<2>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off); break;
-    }
-    LAUNCH_TRY();
-    return B64_OK;
+    return encode_batch_any(src, Msgs{in_off, nullptr}, N, dst, out_off, flags, out_len, workspace,
+                            workspace_bytes, tune, (hipStream_t)stream);
 }
 
 int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
@@ -991,27 +1078,28 @@ int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8
                      int64_t *err_off, void *workspace, int64_t workspace_bytes,
                      const b64_tune *tune, void *stream)
 {
-    if (N < 0) return fail(B64_BAD_ARG, "negative N");
-    if (N == 0) return B64_OK;
-    if (!src || !in_off || !dst || !out_off || !out_len || !err_off) return fail(B64_BAD_ARG, "null argument");
-    int block, upl, grid;
-    int rc = batch_shape(tune, &block, &upl, &grid);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    int64_t *unit_off;
-    rc = plan<B64_DIR_DECODE>(in_off, N, flags, workspace, workspace_bytes, out_len, err_off, &unit_off, s);
-    if (rc) return rc;
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_dec_batch<1>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    case 4: hipLaunchKernelGGL((k_dec_batch<4>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    case 8: hipLaunchKernelGGL((k_dec_batch<8>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    default: hipLaunchKernelGGL((k_dec_batch<2>), grid, block, 0, s, src, in_off, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    }
-    LAUNCH_TRY();
-    const int fb = (int)std::min<int64_t>((N + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_dec_batch_final, fb, 256, 0, s, N, out_len, err_off);
-    LAUNCH_TRY();
-    return B64_OK;
+    return decode_batch_any(src, Msgs{in_off, nullptr}, N, dst, out_off, flags, out_len, err_off,
+                            workspace, workspace_bytes, tune, (hipStream_t)stream);
+}
+
+int b64_encode_batch_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len,
+                            int64_t N, uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                            int64_t *out_len, void *workspace, int64_t workspace_bytes,
+                            const b64_tune *tune, void *stream)
+{
+    if (N > 0 && !in_len) return fail(B64_BAD_ARG, "null in_len");
+    return encode_batch_any(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, out_len, workspace,
+                            workspace_bytes, tune, (hipStream_t)stream);
+}
+
+int b64_decode_batch_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len,
+                            int64_t N, uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                            int64_t *out_len, int64_t *err_off, void *workspace,
+                            int64_t workspace_bytes, const b64_tune *tune, void *stream)
+{
+    if (N > 0 && !in_len) return fail(B64_BAD_ARG, "null in_len");
+    return decode_batch_any(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, out_len, err_off,
+                            workspace, workspace_bytes, tune, (hipStream_t)stream);
 }
 
 int b64_encode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,

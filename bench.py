@@ -30,6 +30,10 @@ METRIC = "encode/decode GB/s & %HBM peak; batched vs per-msg launch; p50/p99 lat
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_single_1GiB.json")
 
 
+def progress(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,6 +42,11 @@ def parse():
     ap.add_argument("--size", type=int, default=1 << 30, help="payload bytes (default 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=1024)
+    ap.add_argument("--quick", action="store_true",
+                    help="only the timed 1 GiB step (skip the config 1, batched and serving reports)")
+    ap.add_argument("--only", default="",
+                    help="comma list of extra reports to run: config1,batched3,batched4,serving")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain int32 copy kernel (1 GiB in, 1 GiB out) three times; "
                          "its HBM counter readings scale the codec's counter readings")
@@ -111,6 +120,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n = args.size
+    progress("generating the 1 GiB workload")
     w = workloads.single_at_fraction(n, seed=1, frac=0.999)
     payload = w["payload"]
     x = torch.from_numpy(payload).to(dev)
@@ -138,6 +148,7 @@ def main():
         codec.decode_async(bad, out_bad, res_bad, stream=stream)
         if ev: ev[3].record(stream)
 
+    progress("timed steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -212,11 +223,213 @@ def main():
         "paper_context": "AVX2 on i7-6700 (Skylake, 3.4 GHz, 1 core): ~0.25 cycles/byte "
                          "(~13.6 GB/s) encode and decode; Chrome 2.7 / 1.8 cycles/byte",
     }
+    text_h = text.cpu().numpy() if not args.no_cpu_baseline else None
+    del x, out, out_bad, bad, text
+    torch.cuda.empty_cache()
+    if not args.quick:
+        wanted = set(filter(None, args.only.split(","))) or {"config1", "batched3", "batched4", "serving"}
+        if "config1" in wanted:
+            progress("config 1 latency")
+            line["config1_latency"] = report_config1()
+        if "batched3" in wanted:
+            progress("config 3 batched vs per-message")
+            line["batched_config3"] = report_batched(3)
+            torch.cuda.empty_cache()
+        if "batched4" in wanted:
+            progress("config 4 batched vs per-message (autotuned)")
+            line["batched_config4"] = report_batched(4)
+            torch.cuda.empty_cache()
+        if "serving" in wanted:
+            progress("config 5 serving")
+            line["serving_config5"] = report_serving(args.serve_seconds)
     if not args.no_cpu_baseline:
-        del x, out, out_bad, bad
-        torch.cuda.empty_cache()
-        line["cpu_baseline"] = cpu_baseline(payload, text.cpu().numpy(), args.cpu_sample_mib)
+        progress("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(payload, text_h, args.cpu_sample_mib)
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- reports --
+
+def _events_ms(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]))
+
+
+def _wall_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def report_config1():
+    """1 MiB single buffer (seed 0): launch/latency bound and cache resident."""
+    import torch
+    from paper_1704_00605_amd import codec, workloads
+
+    dev = torch.device("cuda:0")
+    s = torch.cuda.current_stream()
+    w = workloads.single(1 << 20, seed=0)
+    x = torch.from_numpy(w["payload"]).to(dev)
+    n = x.numel()
+    m = codec.encoded_len(n)
+    t = torch.empty(m, dtype=torch.uint8, device=dev)
+    o = torch.empty(codec.decoded_max(m), dtype=torch.uint8, device=dev)
+    res = torch.zeros(2, dtype=torch.int64, device=dev)
+    codec.encode(x, out=t)
+    bad = t.clone()
+    pos = min(int(np.floor(w["corrupt_u"] * m)), m - 1)
+    bad[pos] = workloads.corruption_byte(w["corrupt_rank"], 0, pos, m)
+    enc_ms = _events_ms(lambda: codec.encode(x, out=t), 50, s)
+    dec_ms = _events_ms(lambda: codec.decode_async(t, o, res), 50, s)
+    dec_sync_ms = _wall_ms(lambda: codec.decode(t, out=o), 50)
+    verdict = codec.decode(bad, out=o)[1]
+    assert verdict == pos and torch.equal(codec.decode(t, out=o)[0], x)
+    return {
+        "workload": "1 MiB uniform random bytes (seed 0), standard alphabet; cache resident, launch bound",
+        "encode_us": round(enc_ms * 1e3, 2), "decode_async_us": round(dec_ms * 1e3, 2),
+        "decode_sync_call_us": round(dec_sync_ms * 1e3, 2),
+        "encode_input_GBps": round(n / enc_ms / 1e6, 1), "decode_input_GBps": round(m / dec_ms / 1e6, 1),
+        "invalid_byte_at": pos, "note": "%HBM peak not meaningful at this size (L2/MALL resident)",
+    }
+
+
+def report_batched(which):
+    """Configs 3/4: one persistent launch per direction over the packed batch
+    (plan + codec kernels, eager and as a HIP graph, default and autotuned
+    launch shape) against one single-buffer launch per message."""
+    import torch
+    from paper_1704_00605_amd import autotune, codec, workloads
+    from paper_1704_00605_amd.graph import BatchGraph
+
+    dev = torch.device("cuda:0")
+    s = torch.cuda.current_stream()
+    if which == 3:
+        w = workloads.uneven()
+        name = "100,000 messages, lengths log-uniform in [1, 65536] (seed 2), standard alphabet, 1% corrupted"
+    else:
+        w = workloads.heavy_mix()
+        name = ("8,192 messages: 819 uniform in [1 MiB, 16 MiB] + 7,373 uniform in [16 B, 4 KiB] (seed 3), "
+                "per-message std/url flag, 0.5% corrupted")
+    off_h = w["in_off"]
+    N = off_h.size - 1
+    flags_h = w["flags"]
+    src = torch.from_numpy(w["payload"]).to(dev)
+    del w["payload"]
+    in_off = torch.from_numpy(off_h).to(dev)
+    flags = torch.from_numpy(flags_h).to(dev)
+    out = {"workload": name, "messages": N, "input_bytes": int(off_h[-1])}
+    for direction, label in ((codec.DIR_ENCODE, "encode"), (codec.DIR_DECODE, "decode")):
+        if direction == codec.DIR_DECODE:
+            # decode input: the encoded batch with the seeded corruptions
+            text_off = enc_off
+            toff_h = text_off.cpu().numpy()
+            text = enc_dst
+            ids, u, rk = w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"]
+            lens = np.diff(toff_h)[ids]
+            pos = np.minimum(np.floor(u * lens).astype(np.int64), np.maximum(lens - 1, 0))
+            vals = [workloads.corruption_byte(r, int(flags_h[i]), int(p), int(L)) for r, i, p, L in zip(rk, ids, pos, lens)]
+            keep = lens > 0
+            text[torch.from_numpy((toff_h[ids] + pos)[keep]).to(dev)] = torch.tensor(np.array(vals, np.uint8)[keep], device=dev)
+            bsrc, boff, boff_h = text, text_off, toff_h
+        else:
+            bsrc, boff, boff_h = src, in_off, off_h
+        out_off = codec.batch_out_offsets(direction, boff, flags)
+        total = int(out_off[-1].item())
+        dst = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+        out_len = torch.empty(N, dtype=torch.int64, device=dev)
+        err = torch.empty(N, dtype=torch.int64, device=dev)
+        ws = codec.Workspace()
+        if direction == codec.DIR_ENCODE:
+            run = lambda tn=None: codec.encode_batch(bsrc, boff, out_off, flags, dst, out_len, tune=tn,
+                                                     workspace=ws, validate=False)
+        else:
+            run = lambda tn=None: codec.decode_batch(bsrc, boff, out_off, flags, dst, out_len, err, tune=tn,
+                                                     workspace=ws, validate=False)
+        run()
+        torch.cuda.synchronize()
+        base_ms = _events_ms(run, 10, s)
+        best, entry = autotune.tune(direction, bsrc, boff, flags, in_off_host=boff_h, reps=3)
+        tuned_ms = _events_ms(lambda: run(best), 10, s)
+        tuned_wall = _wall_ms(lambda: run(best), 5)
+        g = BatchGraph(direction, bsrc, boff, out_off, dst, out_len,
+                       err if direction == codec.DIR_DECODE else None, flags, tune=best)
+        graph_ms = _events_ms(g.launch, 10, s)
+        graph_wall = _wall_ms(g.launch, 5)
+        g.close()
+        # verdicts of the batch (checked against the per-message launches below)
+        b_len = out_len.cpu().numpy().copy()
+        b_err = err.cpu().numpy().copy() if direction == codec.DIR_DECODE else None
+        oo_h = out_off.cpu().numpy()
+        dst2 = torch.empty_like(dst)
+        ol2 = torch.empty(N, dtype=torch.int64, device=dev)
+        er2 = torch.empty(N, dtype=torch.int64, device=dev)
+        if direction == codec.DIR_ENCODE:
+            each = lambda: codec.encode_each(bsrc, boff_h, oo_h, dst2, ol2, h_flags=flags_h)
+        else:
+            each = lambda: codec.decode_each(bsrc, boff_h, oo_h, dst2, ol2, er2, h_flags=flags_h)
+        each_wall = _wall_ms(each, 2)
+        same = bool(np.array_equal(ol2.cpu().numpy(), b_len))
+        if direction == codec.DIR_DECODE:
+            same = same and bool(np.array_equal(er2.cpu().numpy(), b_err))
+        else:
+            same = same and bool(torch.equal(dst2, dst))
+        algo = int(boff_h[-1] - boff_h[0]) + total
+        out[label] = {
+            "batched_ms": round(tuned_ms, 4), "batched_default_shape_ms": round(base_ms, 4),
+            "batched_wall_ms": round(tuned_wall, 4), "graph_replay_ms": round(graph_ms, 4),
+            "graph_wall_ms": round(graph_wall, 4), "per_message_wall_ms": round(each_wall, 4),
+            "speedup_vs_per_message": round(each_wall / tuned_wall, 2),
+            "input_GBps": round((boff_h[-1] - boff_h[0]) / tuned_ms / 1e6, 1),
+            "hbm_GBps_algorithmic": round(algo / tuned_ms / 1e6, 1),
+            "hbm_frac": round(algo / tuned_ms / 1e6 / HBM_PEAK_GBPS, 4),
+            "tune": best, "msgs_per_wg_step": entry.get("msgs_per_wg_step"),
+            "same_verdicts_as_per_message": same,
+        }
+        if direction == codec.DIR_ENCODE:
+            enc_dst, enc_off = dst, out_off
+            out["encode"]["invalid_messages"] = 0
+        else:
+            out["decode"]["invalid_messages"] = int((b_err >= 0).sum())
+    return out
+
+
+def report_serving(seconds):
+    """Config 5: Poisson arrivals at 200,000/s, 50/50 encode/decode, sizes
+    log-uniform in [64 B, 1 MiB], 1% of decodes corrupted; device pool capped
+    at 8 GiB with admission by free memory."""
+    import torch
+    from paper_1704_00605_amd import serve, workloads
+    from paper_1704_00605_amd.pool import DevicePool
+
+    banks = serve.Banks(corpus_bytes=1 << 30, seed=40)
+    tr = workloads.serving_trace(rate=200_000.0, seconds=seconds, seed=4)
+    req = serve.build_requests(tr, banks, seed=41)
+    pool = DevicePool(8 << 30)
+    res, st = serve.run(req, banks, pool, max_batch=4096, tick_us=250, streams=4,
+                        max_seconds=seconds * 6 + 30)
+    summ = serve.summarize(req, res, st)
+    summ.update({"workload": f"Poisson 200,000 req/s for {seconds:g} s (seed 4), 50/50 encode/decode, "
+                             "sizes log-uniform [64 B, 1 MiB], 1% of decodes corrupted",
+                 "offered_GBps": round(float(req['in_len'].sum()) / seconds / 1e9, 3),
+                 "pool_GiB": 8, "rc": res["rc"]})
+    del pool, banks
+    torch.cuda.empty_cache()
+    return summ
 
 
 def kernel_hash():

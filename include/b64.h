@@ -129,23 +129,31 @@ int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, 
 #define B64_DIR_ENCODE 0
 #define B64_DIR_DECODE 1
 
-/* Device exclusive scan of per-message output sizes: out_off[0] = 0 and
- * out_off[i+1] - out_off[i] = 4 * ceil(len_i / 3) (encode) or
- * 3 * floor(len_i / 4) (+2 if the message is unpadded; decode capacity).
- * out_off has N+1 entries. Enqueued on `stream`. */
+/* Device exclusive scan of per-message output slots: out_off[0] = 0 and
+ * out_off[i+1] - out_off[i] = 4 * ceil(len_i / 3) (encode), or the decode
+ * capacity 3 * floor(len_i / 4) (+ max(0, len_i mod 4 - 1) for an unpadded
+ * message) rounded up to a multiple of 4, so that every slot keeps dst's
+ * 4-byte alignment. out_off has N+1 entries. Enqueued on `stream`. */
 int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *out_off,
                           const uint8_t *flags, void *stream);
 
 /* Launch shape of the persistent batched kernels. A zero field means "use
  * the default". block: threads per workgroup (64..1024, multiple of 64);
  * units_per_lane: 12-byte (encode) / 16-character (decode) units each lane
- * carries per step (1, 2, 4 or 8); grid: number of workgroups of the
- * persistent launch (0 = 8 per compute unit); small_msg: reserved, 0. */
+ * carries per step (1, 2, 4 or 8); grid: workgroups of the persistent launch
+ * (0 = 32 per compute unit for layout 0, 8 for layout 1); layout: how the
+ * flattened units of all messages are shared out -
+ *   0  tiles of block * units_per_lane units, grid-stride over the batch
+ *      (blocks in flight cover one dense window; a tile inside one message
+ *      runs the single-buffer step) - best when large messages dominate;
+ *   1  one contiguous range of 64-unit groups per wave, walked with a
+ *      message cursor - best for many small and mid-size messages.
+ * The autotuner picks all four per device and message-size histogram. */
 typedef struct b64_tune {
     int32_t block;
     int32_t units_per_lane;
     int32_t grid;
-    int32_t small_msg;
+    int32_t layout;
 } b64_tune;
 
 /* Device workspace (bytes) the batched calls need for N messages. */
@@ -250,6 +258,7 @@ typedef struct b64_server_cfg {
     int32_t capture;        /* keep outputs allocated after completion */
     int32_t idle_sleep_us;  /* sleep when nothing is in flight or ready (0 = spin) */
     int32_t block, units_per_lane, grid;  /* batched kernel launch shape (0 = default) */
+    int32_t layout;         /* batched work layout, as in b64_tune (1 suits serving mixes) */
     double time_scale;      /* arrival time multiplier (1 = real time, 0 = all at once) */
     double max_seconds;     /* wall-clock limit of the call (0 = 600) */
 } b64_server_cfg;

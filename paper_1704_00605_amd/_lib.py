@@ -32,7 +32,7 @@ DIR_DECODE = 1
 class Tune(ctypes.Structure):
     """``b64_tune``: launch shape of the persistent batched kernels."""
     _fields_ = [("block", ctypes.c_int32), ("units_per_lane", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("small_msg", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -42,7 +42,7 @@ class ServerCfg(ctypes.Structure):
     """``b64_server_cfg``."""
     _fields_ = [("max_batch", ctypes.c_int32), ("tick_us", ctypes.c_int32), ("streams", ctypes.c_int32),
                 ("capture", ctypes.c_int32), ("idle_sleep_us", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("units_per_lane", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("units_per_lane", ctypes.c_int32), ("grid", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("time_scale", ctypes.c_double), ("max_seconds", ctypes.c_double)]
 
 

@@ -1,8 +1,9 @@
 """Autotuner for the persistent batched kernels.
 
-Searches the launch shape (threads per workgroup, units per lane, workgroups
-in the persistent grid) of ``b64_encode_batch`` / ``b64_decode_batch`` on the
-actual batch, timing each candidate with HIP events, and caches the winner in
+Searches the work layout (grid-stride tiles, or one contiguous range of
+64-unit groups per wave) and the launch shape (threads per workgroup, units
+per lane, workgroups in the persistent grid) of ``b64_encode_batch`` /
+``b64_decode_batch`` on the actual batch, timing each candidate with HIP events, and caches the winner in
 a JSON file keyed by device, architecture, direction and a coarse signature
 of the batch (message count, total bytes and the log2 histogram of message
 lengths). The tile of one workgroup step is ``block * units_per_lane``
@@ -19,9 +20,12 @@ import torch
 
 from . import codec
 
-BLOCKS = (128, 256, 512, 1024)
-UNITS = (1, 2, 4, 8)
-GRID_PER_CU = (2, 4, 8, 16)
+# per layout: (blocks, units per lane, workgroups per compute unit)
+SPACE = {
+    0: ((256, 512, 1024), (1, 2, 4), (8, 16, 32)),
+    1: ((128, 256, 512), (1, 2, 4), (4, 8, 16)),
+}
+DEFAULT = {"block": 512, "units_per_lane": 2, "grid_per_cu": 32, "layout": 0}
 
 
 def cache_path():
@@ -69,7 +73,8 @@ def save_cache(c):
 
 
 def candidates(cus):
-    return [dict(block=b, units_per_lane=u, grid=g * cus) for b in BLOCKS for u in UNITS for g in GRID_PER_CU]
+    return [dict(block=b, units_per_lane=u, grid=g * cus, layout=lay)
+            for lay, (blocks, units, grids) in SPACE.items() for b in blocks for u in units for g in grids]
 
 
 def time_call(fn, reps):
@@ -107,9 +112,11 @@ def tune(direction, src, in_off, flags=None, in_off_host=None, reps=3, cands=Non
     t0 = time.perf_counter()
     for c in cands or candidates(cus):
         if direction == codec.DIR_ENCODE:
-            fn = lambda: codec.encode_batch(src, in_off, out_off, flags, dst, out_len, tune=c, workspace=ws)
+            fn = lambda: codec.encode_batch(src, in_off, out_off, flags, dst, out_len, tune=c, workspace=ws,
+                                            validate=False)
         else:
-            fn = lambda: codec.decode_batch(src, in_off, out_off, flags, dst, out_len, err, tune=c, workspace=ws)
+            fn = lambda: codec.decode_batch(src, in_off, out_off, flags, dst, out_len, err, tune=c, workspace=ws,
+                                            validate=False)
         ms = time_call(fn, reps)
         results.append((ms, c))
         if verbose:
@@ -127,7 +134,8 @@ def tune(direction, src, in_off, flags=None, in_off_host=None, reps=3, cands=Non
         "bytes": int(units), "signature": sig,
     }
     for ms, c in results:
-        if c["block"] == 256 and c["units_per_lane"] == 2 and c["grid"] == 8 * cus:
+        if (c["block"], c["units_per_lane"], c["grid"], c["layout"]) == (
+                DEFAULT["block"], DEFAULT["units_per_lane"], DEFAULT["grid_per_cu"] * cus, DEFAULT["layout"]):
             entry["default_ms"] = round(ms, 4)
     if use_cache:
         cache[key] = entry

@@ -44,7 +44,7 @@ def _tune(t):
         return None
     if isinstance(t, Tune):
         return ctypes.byref(t)
-    tt = Tune(**{k: int(v) for k, v in dict(t).items() if k in ("block", "units_per_lane", "grid", "small_msg")})
+    tt = Tune(**{k: int(v) for k, v in dict(t).items() if k in ("block", "units_per_lane", "grid", "layout")})
     return ctypes.byref(tt)
 
 
@@ -110,7 +110,7 @@ def decode_async(src, out, result, alphabet=ALPHABET_STD, stream=None):
 
 
 def set_single_tune(direction, block=0, units_per_lane=0, blocks_per_cu=0):
-    t = Tune(block=block, units_per_lane=units_per_lane, grid=blocks_per_cu, small_msg=0)
+    t = Tune(block=block, units_per_lane=units_per_lane, grid=blocks_per_cu, layout=0)
     check(lib().b64_set_single_tune(int(direction), ctypes.byref(t)), "b64_set_single_tune")
 
 
@@ -249,6 +249,8 @@ def _validate_gather(src, in_begin, in_len, out_off, dst, direction, flags=None)
 
 
 def _gather_out_off(in_len, direction, flags, device):
+    """Output slots laid out like b64_batch_out_offsets (decode slots rounded
+    up to a multiple of 4)."""
     import numpy as np
     n = in_len.cpu().numpy()
     fl = np.zeros(n.size, np.uint8) if flags is None else flags.cpu().numpy()
@@ -256,6 +258,7 @@ def _gather_out_off(in_len, direction, flags, device):
         cap = 4 * ((n + 2) // 3)
     else:
         cap = 3 * (n // 4) + np.where(fl & FLAG_NOPAD, np.maximum(n % 4 - 1, 0), 0)
+        cap = (cap + 3) // 4 * 4
     oo = np.zeros(n.size, np.int64)
     if n.size > 1:
         oo[1:] = np.cumsum(cap)[:-1]

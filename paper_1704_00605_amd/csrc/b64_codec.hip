@@ -275,6 +275,14 @@ __device__ __forceinline__ int64_t dec_cap_of(int64_t len, int nopad)
     return 3 * (len / 4) + ((nopad && (len & 3) >= 2) ? (len & 3) - 1 : 0);
 }
 
+// Decode output slot of the batch layout: the capacity rounded up to a
+// multiple of 4 so every slot starts where dst's alignment allows dword
+// stores (each 16-character unit writes 12 bytes at offset 12j of its slot).
+__device__ __forceinline__ int64_t dec_slot_of(int64_t len, int nopad)
+{
+    return (dec_cap_of(len, nopad) + 3) & ~(int64_t)3;
+}
+
 // Where the messages of a batch are. Packed form: message i is
 // [begin[i], begin[i+1]) (len == nullptr, begin has N + 1 entries). Gather
 // form: message i is [begin[i], begin[i] + len[i]).
@@ -382,11 +390,12 @@ __device__ __forceinline__ int64_t uniform64(int64_t x)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Largest m in [0, N) with unit_off[m] <= t (t < unit_off[N]), found by the
-// whole wave with 64-way probes. Result is wave-uniform.
-__device__ int64_t wave_find_msg(const int64_t *__restrict__ unit_off, int64_t N, int64_t t)
+// Largest m in [lo, N) with unit_off[m] <= t, given unit_off[lo] <= t <
+// unit_off[N], found by the whole wave with 64-way probes. Wave-uniform.
+__device__ int64_t wave_find_msg(const int64_t *__restrict__ unit_off, int64_t N, int64_t t,
+                                 int64_t lo = 0)
 {
-    int64_t lo = 0, hi = N;  // unit_off[lo] <= t < unit_off[hi]
+    int64_t hi = N;  // unit_off[lo] <= t < unit_off[hi]
     const int lane = __lane_id();
     while (hi - lo > 1) {
         const int64_t span = hi - lo;
@@ -431,32 +440,127 @@ __device__ int64_t lane_find_msg(const int64_t *__restrict__ unit_off, int64_t N
     return res;
 }
 
-// Per-lane batched unit description.
-struct UnitRef {
-    int64_t msg;   // message index
-    int64_t j;     // unit index inside the message
+// What one lane works on in a batched step: unit j of message mm.
+struct LaneRef {
     bool valid;
+    int64_t mm, j, b, n, o;
+    int fl;
 };
 
-// Resolves the units gs + lane of one 64-unit group. m is the wave-uniform
-// message of unit gs (updated to the message of the group's last unit).
-__device__ __forceinline__ UnitRef resolve_group(const int64_t *__restrict__ unit_off, int64_t N,
-                                                 int64_t U, int64_t gs, int64_t &m)
+struct BatchArgs {
+    Msgs msgs;
+    int64_t N, U;
+    const int64_t *__restrict__ unit_off;
+    const int64_t *__restrict__ out_off;
+    const uint8_t *__restrict__ flags;
+};
+
+// Per-lane view of unit u, given the message m0 of a unit <= u: the
+// message by a wave-wide search over the next boundaries, then its metadata.
+__device__ __forceinline__ LaneRef lane_ref(const BatchArgs &a, int64_t m0, int64_t u)
 {
-    while (unit_off[m + 1] <= gs) m++;
-    const int64_t u = gs + __lane_id();
-    UnitRef r;
-    r.valid = u < U;
-    if (unit_off[m + 1] >= gs + 64) {
-        r.msg = m;
+    LaneRef r;
+    r.valid = u < a.U;
+    const int64_t mm = lane_find_msg(a.unit_off, a.N, m0, u, r.valid);
+    r.mm = mm;
+    r.j = u - a.unit_off[mm];
+    r.b = a.msgs.b(mm);
+    r.n = a.msgs.n(mm);
+    r.o = a.out_off[mm];
+    r.fl = a.flags ? a.flags[mm] : 0;
+    return r;
+}
+
+// One unit of the batched encode: full 12-byte units, or the message's
+// final partial unit (Algorithm 1's tail).
+__device__ __forceinline__ void enc_batch_unit(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                               const LaneRef &r, bool full, const uint32_t (&w)[3],
+                                               const uint8_t *tabs)
+{
+    const uint8_t *tab = tabs + 64 * (r.fl & M_URL);
+    uint8_t *q = dst + r.o + 16 * r.j;
+    if (full) {
+        uint32_t o[4];
+        enc_unit(w[0], w[1], w[2], tab, o[0], o[1], o[2], o[3]);
+        store_words<4, true>(q, o);
     } else {
-        r.msg = lane_find_msg(unit_off, N, m, u, r.valid);
-        // next group starts at or after the message of the last valid lane
-        const unsigned long long vb = __ballot(r.valid);
-        const int top = 63 - __clzll(vb);
-        m = uniform64(__shfl(r.msg, top, 64));
+        enc_tail(src + r.b + 12 * r.j, (int)(r.n - 12 * r.j), q, tab, r.fl & M_NOPAD);
     }
-    r.j = u - unit_off[r.msg];
+}
+
+// One unit of the batched decode: interior units (16 characters, none of
+// them the message's last) or the final unit with the padding and length
+// rules. Errors lower the message's err_off; the final unit's lane writes
+// the decoded length when that unit is valid.
+__device__ __forceinline__ void dec_batch_unit(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                               const LaneRef &r, bool interior, const uint32_t (&w)[4],
+                                               const uint8_t *tabs, int64_t *__restrict__ out_len,
+                                               int64_t *__restrict__ err_off)
+{
+    const uint8_t *tab = tabs + 256 * (r.fl & M_URL);
+    uint8_t *q = dst + r.o + 12 * r.j;
+    if (interior) {
+        uint32_t o[3];
+        const uint32_t bad = dec_unit(w[0], w[1], w[2], w[3], tab, o[0], o[1], o[2]);
+        store_words<3, true>(q, o);
+        if (bad & INVALID) {
+            const int64_t pos = 16 * r.j + dec_first_bad(w[0], w[1], w[2], w[3], tab);
+            atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)pos);
+        }
+    } else {
+        int nout;
+        const int idx = dec_tail(src + r.b + 16 * r.j, (int)(r.n - 16 * r.j), r.n, q, tab, r.fl, &nout);
+        if (idx >= 0)
+            atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)(16 * r.j + idx));
+        else
+            out_len[r.mm] = 12 * r.j + nout;
+    }
+}
+
+// ---------------------------------------------------------------- layout 1
+// One contiguous share of the 64-unit groups per wave, walked with a
+// wave-uniform cursor: the message holding the wave's current group and its
+// metadata, kept in scalar registers, so that groups inside one message need
+// no metadata loads ahead of their data loads. Suits batches of many small
+// and mid-size messages.
+struct Cursor {
+    int64_t m, u0, u1;  // message, its unit range [u0, u1)
+    int64_t b, n, o;    // input begin, input length, output begin
+    int fl;             // flags
+};
+
+__device__ __forceinline__ void cursor_load(Cursor &c, const BatchArgs &a, int64_t m)
+{
+    c.m = m;
+    c.u0 = a.unit_off[m];
+    c.u1 = a.unit_off[m + 1];
+    c.b = a.msgs.b(m);
+    c.n = a.msgs.n(m);
+    c.o = a.out_off[m];
+    c.fl = a.flags ? a.flags[m] : 0;
+}
+
+// Units gs + lane of one 64-unit group (gs < U); advances the cursor.
+__device__ __forceinline__ LaneRef resolve_group(Cursor &c, const BatchArgs &a, int64_t gs)
+{
+    if (c.u1 <= gs) {  // the group starts in a later message
+        int64_t m = c.m + 1;
+        while (a.unit_off[m + 1] <= gs) m++;  // skips messages without units
+        cursor_load(c, a, m);
+    }
+    const int64_t u = gs + __lane_id();
+    if (gs + 64 <= c.u1) {  // whole group inside the cursor's message
+        LaneRef r;
+        r.valid = true;
+        r.mm = c.m; r.j = u - c.u0; r.b = c.b; r.n = c.n; r.o = c.o; r.fl = c.fl;
+        return r;
+    }
+    const LaneRef r = lane_ref(a, c.m, u);
+    // the next group starts in the message of this group's last valid unit or later
+    const unsigned long long vb = __ballot(r.valid);
+    const int top = 63 - __clzll(vb);
+    const int64_t last = uniform64(__shfl(r.mm, top, 64));
+    if (last != c.m) cursor_load(c, a, last);
     return r;
 }
 
@@ -471,7 +575,7 @@ __device__ __forceinline__ void wave_share(int64_t U, int64_t &g0, int64_t &g1)
 }
 
 template <int UPL>
-__global__ __launch_bounds__(1024) void k_enc_batch(
+__global__ __launch_bounds__(1024) void k_enc_batch_w(
     const uint8_t *__restrict__ src, Msgs msgs, int64_t N,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
     const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off)
@@ -479,13 +583,14 @@ __global__ __launch_bounds__(1024) void k_enc_batch(
     __shared__ uint32_t s_tab[32];
     lds_fill(s_tab, &c_tab.enc[0][0], 128);
     __syncthreads();
-    const int64_t U = unit_off[N];
+    const BatchArgs a{msgs, N, unit_off[N], unit_off, out_off, flags};
     int64_t g0, g1;
-    wave_share(U, g0, g1);
+    wave_share(a.U, g0, g1);
     if (g0 >= g1) return;
-    int64_t m = wave_find_msg(unit_off, N, g0 * 64);
+    Cursor c;
+    cursor_load(c, a, wave_find_msg(unit_off, N, g0 * 64));
     for (int64_t g = g0; g < g1; g += UPL) {
-        UnitRef r[UPL];
+        LaneRef r[UPL];
         uint32_t w[UPL][3];
         bool full[UPL];
 #pragma unroll
@@ -493,37 +598,19 @@ __global__ __launch_bounds__(1024) void k_enc_batch(
             r[k].valid = false;
             full[k] = false;
             if (g + k < g1) {
-                r[k] = resolve_group(unit_off, N, U, (g + k) * 64, m);
-                if (r[k].valid) {
-                    const int64_t b = msgs.b(r[k].msg);
-                    const int64_t len = msgs.n(r[k].msg);
-                    full[k] = 12 * r[k].j + 12 <= len;
-                    if (full[k]) load12(src + b + 12 * r[k].j, w[k][0], w[k][1], w[k][2]);
-                }
+                r[k] = resolve_group(c, a, (g + k) * 64);
+                full[k] = r[k].valid && 12 * r[k].j + 12 <= r[k].n;
+                if (full[k]) load12(src + r[k].b + 12 * r[k].j, w[k][0], w[k][1], w[k][2]);
             }
         }
 #pragma unroll
-        for (int k = 0; k < UPL; k++) {
-            if (!r[k].valid) continue;
-            const int64_t mm = r[k].msg;
-            const int fl = flags ? flags[mm] : 0;
-            const uint8_t *tab = (const uint8_t *)s_tab + 64 * (fl & M_URL);
-            uint8_t *q = dst + out_off[mm] + 16 * r[k].j;
-            if (full[k]) {
-                uint32_t o[4];
-                enc_unit(w[k][0], w[k][1], w[k][2], tab, o[0], o[1], o[2], o[3]);
-                store_words<4>(q, o);
-            } else {
-                const int64_t b = msgs.b(mm);
-                const int rem = (int)(msgs.n(mm) - 12 * r[k].j);
-                enc_tail(src + b + 12 * r[k].j, rem, q, tab, fl & M_NOPAD);
-            }
-        }
+        for (int k = 0; k < UPL; k++)
+            if (r[k].valid) enc_batch_unit(src, dst, r[k], full[k], w[k], (const uint8_t *)s_tab);
     }
 }
 
 template <int UPL>
-__global__ __launch_bounds__(1024) void k_dec_batch(
+__global__ __launch_bounds__(1024) void k_dec_batch_w(
     const uint8_t *__restrict__ src, Msgs msgs, int64_t N,
     uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
     const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off,
@@ -532,13 +619,14 @@ __global__ __launch_bounds__(1024) void k_dec_batch(
     __shared__ uint32_t s_tab[128];
     lds_fill(s_tab, &c_tab.dec[0][0], 512);
     __syncthreads();
-    const int64_t U = unit_off[N];
+    const BatchArgs a{msgs, N, unit_off[N], unit_off, out_off, flags};
     int64_t g0, g1;
-    wave_share(U, g0, g1);
+    wave_share(a.U, g0, g1);
     if (g0 >= g1) return;
-    int64_t m = wave_find_msg(unit_off, N, g0 * 64);
+    Cursor c;
+    cursor_load(c, a, wave_find_msg(unit_off, N, g0 * 64));
     for (int64_t g = g0; g < g1; g += UPL) {
-        UnitRef r[UPL];
+        LaneRef r[UPL];
         uint32_t w[UPL][4];
         bool interior[UPL];
 #pragma unroll
@@ -546,44 +634,139 @@ __global__ __launch_bounds__(1024) void k_dec_batch(
             r[k].valid = false;
             interior[k] = false;
             if (g + k < g1) {
-                r[k] = resolve_group(unit_off, N, U, (g + k) * 64, m);
-                if (r[k].valid) {
-                    const int64_t b = msgs.b(r[k].msg);
-                    const int64_t len = msgs.n(r[k].msg);
-                    interior[k] = 16 * r[k].j + 16 < len;  // not the message's last unit
-                    if (interior[k])
-                        load16(src + b + 16 * r[k].j, w[k][0], w[k][1], w[k][2], w[k][3]);
-                }
+                r[k] = resolve_group(c, a, (g + k) * 64);
+                interior[k] = r[k].valid && 16 * r[k].j + 16 < r[k].n;
+                if (interior[k]) load16(src + r[k].b + 16 * r[k].j, w[k][0], w[k][1], w[k][2], w[k][3]);
             }
         }
 #pragma unroll
-        for (int k = 0; k < UPL; k++) {
-            if (!r[k].valid) continue;
-            const int64_t mm = r[k].msg;
-            const int fl = flags ? flags[mm] : 0;
-            const uint8_t *tab = (const uint8_t *)s_tab + 256 * (fl & M_URL);
-            uint8_t *q = dst + out_off[mm] + 12 * r[k].j;
-            const int64_t b = msgs.b(mm);
-            if (interior[k]) {
-                uint32_t o[3];
-                const uint32_t bad = dec_unit(w[k][0], w[k][1], w[k][2], w[k][3], tab, o[0], o[1], o[2]);
-                store_words<3>(q, o);
-                if (bad & INVALID) {
-                    const int64_t pos = 16 * r[k].j + dec_first_bad(w[k][0], w[k][1], w[k][2], w[k][3], tab);
-                    atomicMin((unsigned long long *)&err_off[mm], (unsigned long long)pos);
-                }
-            } else {
-                const int64_t len = msgs.n(mm);
-                const int rem = (int)(len - 16 * r[k].j);
-                int nout;
-                const int idx = dec_tail(src + b + 16 * r[k].j, rem, len, q, tab, fl, &nout);
-                if (idx >= 0)
-                    atomicMin((unsigned long long *)&err_off[mm], (unsigned long long)(16 * r[k].j + idx));
-                else
-                    out_len[mm] = 12 * r[k].j + nout;
-            }
+        for (int k = 0; k < UPL; k++)
+            if (r[k].valid)
+                dec_batch_unit(src, dst, r[k], interior[k], w[k], (const uint8_t *)s_tab, out_len, err_off);
+    }
+}
+
+// ---------------------------------------------------------------- layout 0
+// Layout 0 (tiles): tiles of blockDim * UPL units are dealt out grid-stride,
+// so the blocks in flight stream through one dense window of memory as a
+// one-shot grid does. A block-wide search (bounded below by the block's
+// previous tile) finds each tile's first message. A tile made of full units
+// of one message runs the single-buffer step; any other tile resolves the
+// message of every unit per lane. This suits batches dominated by large
+// messages.
+// Largest m in [lo, N) with unit_off[m] <= t, given unit_off[lo] <= t <
+// unit_off[N]: all threads of the block probe blockDim.x points per round.
+__device__ int64_t block_find_msg(const int64_t *__restrict__ unit_off, int64_t N, int64_t t, int64_t lo)
+{
+    int64_t hi = N;
+    while (hi - lo > 1) {
+        const int64_t stepw = (hi - lo + blockDim.x - 1) / blockDim.x;
+        const int64_t p = lo + (int64_t)(threadIdx.x + 1) * stepw;
+        const int ok = p < hi && unit_off[p] <= t;
+        const int64_t cnt = __syncthreads_count(ok);  // probes increase: ok holds for a prefix
+        const int64_t nlo = lo + cnt * stepw;
+        hi = min(hi, lo + (cnt + 1) * stepw);
+        lo = nlo;
+    }
+    return lo;
+}
+
+template <int UPL, class Fast, class General>
+__device__ __forceinline__ void batch_tiles(const BatchArgs &a, Fast fast, General general, bool decode)
+{
+    const int64_t tile = (int64_t)blockDim.x * UPL;
+    int64_t m = 0;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < a.U; t0 += (int64_t)gridDim.x * tile) {
+        m = block_find_msg(a.unit_off, a.N, t0, m);
+        const int64_t t1 = min(t0 + tile, a.U);
+        const int64_t u0 = a.unit_off[m];
+        const int64_t n = a.msgs.n(m);
+        // units of message m that are full (encode: all 12 bytes in range) or
+        // interior (decode: not the message's last unit)
+        const int64_t full = decode ? (n - 1) / 16 : n / 12;
+        if (t1 <= u0 + full) {
+            fast(m, t0, t1, u0);
+        } else {
+#pragma unroll 1
+            for (int k = 0; k < UPL; k++) general(m, t0 + (int64_t)k * blockDim.x + threadIdx.x);
         }
     }
+}
+
+template <int UPL>
+__global__ __launch_bounds__(1024) void k_enc_batch_t(
+    const uint8_t *__restrict__ src, Msgs msgs, int64_t N,
+    uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
+    const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off)
+{
+    __shared__ uint32_t s_tab[32];
+    lds_fill(s_tab, &c_tab.enc[0][0], 128);
+    __syncthreads();
+    const BatchArgs a{msgs, N, unit_off[N], unit_off, out_off, flags};
+    const uint8_t *tabs = (const uint8_t *)s_tab;
+    auto fast = [&](int64_t m, int64_t t0, int64_t t1, int64_t u0) {
+        const uint8_t *p = src + msgs.b(m);
+        uint8_t *q = dst + out_off[m];
+        const int fl = flags ? flags[m] : 0;
+        const uint8_t *tab = tabs + 64 * (fl & M_URL);
+        const int64_t j0 = t0 - u0, j1 = t1 - u0;
+        const bool whole = t1 - t0 == (int64_t)blockDim.x * UPL;
+        if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0) {
+            if (whole) enc_step<true, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab);
+            else enc_step<true, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab);
+        } else {
+            if (whole) enc_step<false, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab);
+            else enc_step<false, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab);
+        }
+    };
+    auto general = [&](int64_t m0, int64_t u) {
+        const LaneRef r = lane_ref(a, m0, u);
+        if (!r.valid) return;
+        const bool full = 12 * r.j + 12 <= r.n;
+        uint32_t w[3];
+        if (full) load12(src + r.b + 12 * r.j, w[0], w[1], w[2]);
+        enc_batch_unit(src, dst, r, full, w, tabs);
+    };
+    batch_tiles<UPL>(a, fast, general, false);
+}
+
+template <int UPL>
+__global__ __launch_bounds__(1024) void k_dec_batch_t(
+    const uint8_t *__restrict__ src, Msgs msgs, int64_t N,
+    uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
+    const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off,
+    int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
+{
+    __shared__ uint32_t s_tab[128];
+    lds_fill(s_tab, &c_tab.dec[0][0], 512);
+    __syncthreads();
+    const BatchArgs a{msgs, N, unit_off[N], unit_off, out_off, flags};
+    const uint8_t *tabs = (const uint8_t *)s_tab;
+    auto fast = [&](int64_t m, int64_t t0, int64_t t1, int64_t u0) {
+        const uint8_t *p = src + msgs.b(m);
+        uint8_t *q = dst + out_off[m];
+        const int fl = flags ? flags[m] : 0;
+        const uint8_t *tab = tabs + 256 * (fl & M_URL);
+        unsigned long long *slot = (unsigned long long *)&err_off[m];
+        const int64_t j0 = t0 - u0, j1 = t1 - u0;
+        const bool whole = t1 - t0 == (int64_t)blockDim.x * UPL;
+        if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0) {
+            if (whole) dec_step<true, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
+            else dec_step<true, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
+        } else {
+            if (whole) dec_step<false, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
+            else dec_step<false, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
+        }
+    };
+    auto general = [&](int64_t m0, int64_t u) {
+        const LaneRef r = lane_ref(a, m0, u);
+        if (!r.valid) return;
+        const bool interior = 16 * r.j + 16 < r.n;
+        uint32_t w[4];
+        if (interior) load16(src + r.b + 16 * r.j, w[0], w[1], w[2], w[3]);
+        dec_batch_unit(src, dst, r, interior, w, tabs, out_len, err_off);
+    };
+    batch_tiles<UPL>(a, fast, general, true);
 }
 
 __global__ void k_dec_batch_final(int64_t N, int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
@@ -608,14 +791,14 @@ __global__ __launch_bounds__(1024) void k_out_offsets(int dir, Msgs msgs, int64_
     for (int64_t i = i0; i < i1; i++) {
         const int64_t len = msgs.n(i);
         const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
-        s += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_cap_of(len, nopad);
+        s += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
     }
     int64_t acc = block_exclusive_scan(s);
     for (int64_t i = i0; i < i1; i++) {
         out_off[i] = acc;
         const int64_t len = msgs.n(i);
         const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
-        acc += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_cap_of(len, nopad);
+        acc += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
     }
     if (i0 < N && i1 == N) out_off[N] = acc;
     if (N == 0 && threadIdx.x == 0) out_off[0] = 0;
@@ -939,14 +1122,20 @@ int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *ou
 
 namespace {
 
-int batch_shape(const b64_tune *t, int *block, int *upl, int *grid)
+// Launch shape of the batched kernels: tuned values or the defaults
+// (layout 0, 512 threads x 2 units, 32 workgroups per CU: the best shape of
+// the tile layout on large messages on MI355X).
+int batch_shape(const b64_tune *t, int *block, int *upl, int *grid, int *layout)
 {
     int cus;
     int rc = device_cus(&cus);
     if (rc) return rc;
-    *block = (t && t->block) ? t->block : 256;
+    *layout = t ? t->layout : 0;
+    const bool tiles = *layout == 0;
+    *block = (t && t->block) ? t->block : (tiles ? 512 : 256);
     *upl = (t && t->units_per_lane) ? t->units_per_lane : 2;
-    *grid = (t && t->grid) ? t->grid : cus * 8;
+    *grid = (t && t->grid) ? t->grid : cus * (tiles ? 32 : 8);
+    if (*layout != 0 && *layout != 1) return fail(B64_BAD_ARG, "bad layout %d", *layout);
     if (*block < 64 || *block > 1024 || (*block & 63)) return fail(B64_BAD_ARG, "bad block size %d", *block);
     if (*upl != 1 && *upl != 2 && *upl != 4 && *upl != 8) return fail(B64_BAD_ARG, "bad units_per_lane %d", *upl);
     if (*grid < 1 || *grid > (1 << 20)) return fail(B64_BAD_ARG, "bad grid %d", *grid);
@@ -969,17 +1158,24 @@ int plan(Msgs msgs, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes,
     return B64_OK;
 }
 
+#define B64_LAUNCH_UPL(KERN, UPL, ...)                                                   \
+    switch (UPL) {                                                                       \
+    case 1: hipLaunchKernelGGL((KERN<1>), grid, block, 0, s, __VA_ARGS__); break;        \
+    case 4: hipLaunchKernelGGL((KERN<4>), grid, block, 0, s, __VA_ARGS__); break;        \
+    case 8: hipLaunchKernelGGL((KERN<8>), grid, block, 0, s, __VA_ARGS__); break;        \
+    default: hipLaunchKernelGGL((KERN<2>), grid, block, 0, s, __VA_ARGS__); break;       \
+    }
+
 int launch_enc_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
                      const uint8_t *flags, const int64_t *unit_off, const b64_tune *tune, hipStream_t s)
 {
-    int block, upl, grid;
-    int rc = batch_shape(tune, &block, &upl, &grid);
+    int block, upl, grid, layout;
+    int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_enc_batch<1>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
-    case 4: hipLaunchKernelGGL((k_enc_batch<4>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
-    case 8: hipLaunchKernelGGL((k_enc_batch<8>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
-    default: hipLaunchKernelGGL((k_enc_batch<2>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off); break;
+    if (layout == 1) {
+        B64_LAUNCH_UPL(k_enc_batch_w, upl, src, msgs, N, dst, out_off, flags, unit_off);
+    } else {
+        B64_LAUNCH_UPL(k_enc_batch_t, upl, src, msgs, N, dst, out_off, flags, unit_off);
     }
     LAUNCH_TRY();
     return B64_OK;
@@ -989,14 +1185,13 @@ int launch_dec_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
                      const uint8_t *flags, const int64_t *unit_off, int64_t *out_len, int64_t *err_off,
                      const b64_tune *tune, hipStream_t s)
 {
-    int block, upl, grid;
-    int rc = batch_shape(tune, &block, &upl, &grid);
+    int block, upl, grid, layout;
+    int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_dec_batch<1>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    case 4: hipLaunchKernelGGL((k_dec_batch<4>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    case 8: hipLaunchKernelGGL((k_dec_batch<8>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
-    default: hipLaunchKernelGGL((k_dec_batch<2>), grid, block, 0, s, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off); break;
+    if (layout == 1) {
+        B64_LAUNCH_UPL(k_dec_batch_w, upl, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off);
+    } else {
+        B64_LAUNCH_UPL(k_dec_batch_t, upl, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off);
     }
     LAUNCH_TRY();
     const int fb = (int)std::min<int64_t>((N + 255) / 256, 1024);
@@ -1012,8 +1207,8 @@ int encode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
     if (N < 0) return fail(B64_BAD_ARG, "negative N");
     if (N == 0) return B64_OK;
     if (!src || !msgs.begin || !dst || !out_off || !out_len) return fail(B64_BAD_ARG, "null argument");
-    int block, upl, grid;
-    int rc = batch_shape(tune, &block, &upl, &grid);
+    int block, upl, grid, layout;
+    int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
     int64_t *unit_off;
     rc = plan<B64_DIR_ENCODE>(msgs, N, flags, ws, ws_bytes, out_len, nullptr, &unit_off, s);
@@ -1028,8 +1223,8 @@ int decode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
     if (N < 0) return fail(B64_BAD_ARG, "negative N");
     if (N == 0) return B64_OK;
     if (!src || !msgs.begin || !dst || !out_off || !out_len || !err_off) return fail(B64_BAD_ARG, "null argument");
-    int block, upl, grid;
-    int rc = batch_shape(tune, &block, &upl, &grid);
+    int block, upl, grid, layout;
+    int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
     int64_t *unit_off;
     rc = plan<B64_DIR_DECODE>(msgs, N, flags, ws, ws_bytes, out_len, err_off, &unit_off, s);

@@ -235,7 +235,7 @@ __device__ __forceinline__ void store_edge_lo(uint8_t *q, uint32_t v, uint32_t n
     if (nbytes & 1) { q[0] = (uint8_t)v; }
 }
 
-template <int K>
+template <int K, bool NT = false>
 __device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
 {
     const uintptr_t a = (uintptr_t)q;
@@ -243,7 +243,10 @@ __device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
     if (s == 0) {
         uint32_t *d = (uint32_t *)q;
 #pragma unroll
-        for (int k = 0; k < K; k++) d[k] = o[k];
+        for (int k = 0; k < K; k++) {
+            if (NT) __builtin_nontemporal_store(o[k], d + k);  // streamed: written once, not re-read
+            else d[k] = o[k];
+        }
         return;
     }
     // bytes land at offset s of the aligned window d[0 .. K]

@@ -301,18 +301,19 @@ struct Slot {
     std::vector<int64_t> reqs;
 };
 
-// Layout (int64 words) of a slot's descriptor block for up to B messages:
-// in_begin[B] | in_len[B] | out_off[B] | unit_off[B+1] | out_len[B] | err_off[B] | flags (B bytes)
+// Layout (int64 words) of the descriptor block of a batch of n messages,
+// packed so that one upload moves exactly what the batch needs:
+// in_begin[n] | in_len[n] | out_off[n] | unit_off[n+1] | out_len[n] | err_off[n] | flags (n bytes)
 struct Layout {
-    int64_t B;
+    int64_t n;
     int64_t in_begin() const { return 0; }
-    int64_t in_len() const { return B; }
-    int64_t out_off() const { return 2 * B; }
-    int64_t unit_off() const { return 3 * B; }
-    int64_t out_len() const { return 4 * B + 1; }
-    int64_t err_off() const { return 5 * B + 1; }
-    int64_t flags() const { return 6 * B + 1; }
-    int64_t words() const { return 6 * B + 1 + (B + 7) / 8; }
+    int64_t in_len() const { return n; }
+    int64_t out_off() const { return 2 * n; }
+    int64_t unit_off() const { return 3 * n; }
+    int64_t out_len() const { return 4 * n + 1; }
+    int64_t err_off() const { return 5 * n + 1; }
+    int64_t flags() const { return 6 * n + 1; }
+    int64_t words() const { return 6 * n + 1 + (n + 7) / 8; }
 };
 
 struct Ready {
@@ -340,14 +341,17 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             in_begin[r] > lim - in_len[r] || (in_len[r] > 0 && !bank) || (r && t_arrival[r] < t_arrival[r - 1]))
             return b64i_fail(B64_BAD_ARG, "request outside its bank, bad op or unsorted arrivals");
     }
-    if (cfg->max_batch < 1 || cfg->streams < 1 || cfg->streams > 16 || cfg->tick_us < 0)
+    if (cfg->max_batch < 1 || cfg->streams < 1 || cfg->streams > 16 || cfg->tick_us < 0 ||
+        (cfg->layout != 0 && cfg->layout != 1))
         return b64i_fail(B64_BAD_ARG, "bad server configuration");
     const int64_t B = cfg->max_batch;
-    const Layout L{B};
+    const Layout LB{B};  // largest batch: sizes the slot buffers
     const double max_s = cfg->max_seconds > 0 ? cfg->max_seconds : 600.0;
     const double tick = cfg->tick_us * 1e-6;
-    b64_tune tune{cfg->block, cfg->units_per_lane, cfg->grid, 0};
+    b64_tune tune{cfg->block, cfg->units_per_lane, cfg->grid, cfg->layout};
 
+    const int cus = b64_device_cus();
+    if (cus <= 0) return cus < 0 ? cus : b64i_fail(B64_HIP_ERROR, "no compute units");
     std::vector<Slot> slots(cfg->streams);
     auto cleanup = [&]() {
         for (auto &s : slots) {
@@ -361,8 +365,8 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
     for (auto &s : slots) {
         hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s.h, 8 * L.words(), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc((void **)&s.d, 8 * L.words());
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s.h, 8 * LB.words(), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void **)&s.d, 8 * LB.words());
         if (e != hipSuccess) {
             cleanup();
             return hip_fail(e, "server slot setup");
@@ -390,6 +394,7 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
     auto launch = [&](Slot &s, int dir, double t) -> int {
         auto &q = ready[dir];
         const int64_t n = std::min<int64_t>(B, (int64_t)q.size());
+        const Layout L{n};
         s.reqs.clear();
         int64_t *h = s.h;
         int64_t u = 0;
@@ -408,6 +413,21 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             hf[i] = flags ? flags[r] : 0;
         }
         h[L.unit_off() + n] = u;
+        // grid sized from the batch (a configured grid wins): per-wave ranges
+        // take about 4 groups of 64 units per wave, at most 8 workgroups per
+        // CU; tiles take one workgroup per tile, at most 32 per CU
+        b64_tune bt = tune;
+        if (!cfg->grid) {
+            int64_t want;
+            if (bt.layout == 1) {
+                const int64_t block = bt.block ? bt.block : 256;
+                want = std::min<int64_t>(((u + 63) / 64 + 4 * (block / 64) - 1) / (4 * (block / 64)), 8 * cus);
+            } else {
+                const int64_t tile = (int64_t)(bt.block ? bt.block : 512) * (bt.units_per_lane ? bt.units_per_lane : 2);
+                want = std::min<int64_t>((u + tile - 1) / tile, 32 * cus);
+            }
+            bt.grid = (int32_t)std::max<int64_t>(1, want);
+        }
         int64_t *d = s.d;
         hipError_t e = hipMemcpyAsync(d, h, 8 * L.words(), hipMemcpyHostToDevice, s.stream);
         if (e != hipSuccess) return hip_fail(e, "descriptor upload");
@@ -415,13 +435,13 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
         int r2;
         if (dir == B64_DIR_ENCODE)
             r2 = b64i_encode_planned(enc_src, d + L.in_begin(), d + L.in_len(), n, pool_base, d + L.out_off(),
-                                     df, d + L.unit_off(), &tune, s.stream);
+                                     df, d + L.unit_off(), &bt, s.stream);
         else
             r2 = b64i_decode_planned(dec_src, d + L.in_begin(), d + L.in_len(), n, pool_base, d + L.out_off(),
-                                     df, d + L.unit_off(), d + L.out_len(), d + L.err_off(), &tune, s.stream);
+                                     df, d + L.unit_off(), d + L.out_len(), d + L.err_off(), &bt, s.stream);
         if (r2 != B64_OK) return r2;
         if (dir == B64_DIR_DECODE) {
-            e = hipMemcpyAsync(h + L.out_len(), d + L.out_len(), 16 * B, hipMemcpyDeviceToHost, s.stream);
+            e = hipMemcpyAsync(h + L.out_len(), d + L.out_len(), 16 * n, hipMemcpyDeviceToHost, s.stream);
             if (e != hipSuccess) return hip_fail(e, "verdict readback");
         }
         e = hipEventRecord(s.done, s.stream);
@@ -448,6 +468,7 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             if (q == hipErrorNotReady) { inflight++; continue; }
             if (q != hipSuccess) { rc = hip_fail(q, "hipEventQuery"); break; }
             const double td = now_s();
+            const Layout L{(int64_t)s.reqs.size()};
             for (size_t i = 0; i < s.reqs.size(); i++) {
                 const int64_t r = s.reqs[i];
                 t_done[r] = td;

@@ -80,12 +80,13 @@ def run(requests, banks, pool, max_batch=2048, tick_us=200, streams=4, capture=F
     """Runs the native serving loop. Returns (per-request results, stats)."""
     n = requests["t_arrival"].size
     cfg = ServerCfg(max_batch=max_batch, tick_us=tick_us, streams=streams, capture=int(capture),
-                    idle_sleep_us=idle_sleep_us, block=0, units_per_lane=0, grid=0,
+                    idle_sleep_us=idle_sleep_us, block=0, units_per_lane=0, grid=0, layout=1,
                     time_scale=time_scale, max_seconds=max_seconds)
     if tune:
         cfg.block = tune.get("block", 0)
         cfg.units_per_lane = tune.get("units_per_lane", 0)
         cfg.grid = tune.get("grid", 0)
+        cfg.layout = tune.get("layout", 1)
     t_arr = np.ascontiguousarray(requests["t_arrival"], dtype=np.float64)
     op = np.ascontiguousarray(requests["op"], dtype=np.uint8)
     ib = np.ascontiguousarray(requests["in_begin"], dtype=np.int64)

@@ -45,26 +45,41 @@ def check_encode(data, off, flags=None, tune=None):
     return dst, out_off
 
 
+def dec_slots(toff, flags=None):
+    """Decode slot layout: capacity rounded up to a multiple of 4."""
+    lens = np.diff(toff)
+    fl = np.zeros(lens.size, np.uint8) if flags is None else flags
+    cap = 3 * (lens // 4) + np.where(fl & 4, np.maximum(lens % 4 - 1, 0), 0)
+    slot = (cap + 3) // 4 * 4
+    off = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(slot, out=off[1:])
+    return off
+
+
+def segments(buf, starts, lens):
+    """Concatenation of buf[starts[i] : starts[i] + lens[i]] over i."""
+    lens = np.maximum(lens, 0)
+    if lens.sum() == 0:
+        return np.zeros(0, buf.dtype)
+    idx = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(lens.sum())
+    return buf[idx]
+
+
 def check_decode(text, toff, flags=None, tune=None):
     want, want_off, want_len, want_err = oracle.decode_batch(text, toff, flags)
     fl = None if flags is None else dev(flags)
     dst, out_off, out_len, err = codec.decode_batch(dev(text), dev(toff), flags=fl, tune=tune)
-    assert np.array_equal(host(out_off), want_off)
+    assert np.array_equal(host(out_off), dec_slots(toff, flags))
     gl, ge = host(out_len), host(err)
     bad = np.nonzero((gl != want_len) | (ge != want_err))[0]
     assert bad.size == 0, f"{bad.size} messages differ, first {bad[:5]}: got {gl[bad[:5]]},{ge[bad[:5]]} want {want_len[bad[:5]]},{want_err[bad[:5]]}"
-    # decoded bytes of valid messages; the rest of each capacity slot (and
-    # the whole slot of an invalid message) is unspecified
-    mask = decoded_mask(want_off, want_len, want.size)
-    assert np.array_equal(host(dst)[: want.size][mask], want[mask])
+    # decoded bytes of valid messages; the rest of each slot (and the whole
+    # slot of an invalid message) is unspecified
+    ok = want_len > 0
+    got_b = segments(host(dst), host(out_off)[:-1][ok], want_len[ok])
+    want_b = segments(want, want_off[:-1][ok], want_len[ok])
+    assert np.array_equal(got_b, want_b)
     return gl, ge
-
-
-def decoded_mask(out_off, out_len, size):
-    mask = np.zeros(size, dtype=bool)
-    for i in np.nonzero(out_len > 0)[0]:
-        mask[out_off[i]:out_off[i] + out_len[i]] = True
-    return mask
 
 
 def encode_text(data, off, flags=None):
@@ -81,14 +96,15 @@ def test_encode_batch_shapes(lens):
     check_encode(data, off)
 
 
-def test_encode_batch_random_mix_with_alphabets():
+@pytest.mark.parametrize("layout", [0, 1])
+def test_encode_batch_random_mix_with_alphabets(layout):
     rng = np.random.default_rng(1)
     for trial in range(6):
         N = int(rng.integers(1, 3000))
         lens = np.where(rng.uniform(size=N) < 0.05, rng.integers(5000, 300_000, N), rng.integers(0, 200, N))
         data, off = packed(lens, trial)
         flags = rng.integers(0, 2, N).astype(np.uint8)
-        check_encode(data, off, flags)
+        check_encode(data, off, flags, tune=dict(layout=layout))
 
 
 def test_encode_batch_unaligned_starts():
@@ -97,9 +113,11 @@ def test_encode_batch_unaligned_starts():
     check_encode(data, off)
 
 
-@pytest.mark.parametrize("tune", [dict(block=64, units_per_lane=1, grid=1), dict(block=1024, units_per_lane=8, grid=3),
-                                  dict(block=256, units_per_lane=4, grid=4096), dict(block=128, units_per_lane=2, grid=17)])
-def test_batch_launch_shapes_agree(tune):
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("shape", [dict(block=64, units_per_lane=1, grid=1), dict(block=1024, units_per_lane=8, grid=3),
+                                   dict(block=256, units_per_lane=4, grid=4096), dict(block=128, units_per_lane=2, grid=17)])
+def test_batch_launch_shapes_agree(shape, layout):
+    tune = dict(shape, layout=layout)
     rng = np.random.default_rng(9)
     lens = np.concatenate([rng.integers(0, 100, 2000), rng.integers(10_000, 100_000, 30)])
     rng.shuffle(lens)
@@ -109,7 +127,8 @@ def test_batch_launch_shapes_agree(tune):
     check_decode(text, toff, tune=tune)
 
 
-def test_decode_batch_valid_and_corrupted():
+@pytest.mark.parametrize("layout", [0, 1])
+def test_decode_batch_valid_and_corrupted(layout):
     rng = np.random.default_rng(2)
     for trial in range(5):
         N = int(rng.integers(1, 4000))
@@ -120,7 +139,7 @@ def test_decode_batch_valid_and_corrupted():
         k = max(1, N // 20)
         ids = rng.choice(N, size=k, replace=False)
         workloads.corrupt_text(text, toff, ids, rng.uniform(size=k), rng.integers(0, 192, k), flags)
-        gl, ge = check_decode(text, toff, flags)
+        gl, ge = check_decode(text, toff, flags, tune=dict(layout=layout))
         assert (ge >= 0).sum() >= 1
 
 
@@ -144,8 +163,9 @@ def test_decode_batch_garbage_lengths_and_padding():
     toff = np.zeros(lens.size + 1, dtype=np.int64)
     np.cumsum(lens, out=toff[1:])
     text = np.concatenate(msgs)
-    check_decode(text, toff)
-    check_decode(text, toff, np.ones(lens.size, np.uint8))
+    for layout in (0, 1):
+        check_decode(text, toff, tune=dict(layout=layout))
+        check_decode(text, toff, np.ones(lens.size, np.uint8), tune=dict(layout=layout))
 
 
 def test_batch_matches_single_and_each():
@@ -170,9 +190,7 @@ def test_batch_matches_single_and_each():
     ids = rng.choice(lens.size, size=k, replace=False)
     workloads.corrupt_text(text, toff, ids, rng.uniform(size=k), rng.integers(0, 192, k), flags)
     gl, ge = check_decode(text, toff, flags)
-    dcap = 3 * (np.diff(toff) // 4)
-    doff = np.zeros(lens.size + 1, np.int64)
-    np.cumsum(dcap, out=doff[1:])
+    doff = dec_slots(toff)
     ddst = torch.zeros(max(int(doff[-1]), 1), dtype=torch.uint8, device=DEV)
     dl = torch.zeros(lens.size, dtype=torch.int64, device=DEV)
     de = torch.zeros(lens.size, dtype=torch.int64, device=DEV)
@@ -257,7 +275,4 @@ def test_out_offsets_scan_sizes():
         d = host(codec.batch_out_offsets(D, dev(off), flags=dev(fl) if N else None))
         we = np.zeros(N + 1, np.int64)
         np.cumsum(4 * ((lens + 2) // 3), out=we[1:])
-        cap = 3 * (lens // 4) + np.where(fl & 4, np.maximum(lens % 4 - 1, 0), 0)
-        wd = np.zeros(N + 1, np.int64)
-        np.cumsum(cap, out=wd[1:])
-        assert np.array_equal(e, we) and np.array_equal(d, wd)
+        assert np.array_equal(e, we) and np.array_equal(d, dec_slots(off, fl))

@@ -68,7 +68,7 @@ def test_argument_errors_need_no_gpu(L):
     assert L.b64_batch_workspace_bytes(100000) >= 8 * 100001
     assert L.b64_encode_batch(None, None, -1, None, None, None, None, None, 0, None, None) == _lib.BAD_ARG
     assert L.b64_encode_batch(None, None, 0, None, None, None, None, None, 0, None, None) == 0
-    bad = _lib.Tune(block=100, units_per_lane=0, grid=0, small_msg=0)
+    bad = _lib.Tune(block=100, units_per_lane=0, grid=0, layout=0)
     assert L.b64_set_single_tune(0, ctypes.byref(bad)) == _lib.BAD_ARG
     assert L.b64_set_single_tune(5, ctypes.byref(bad)) == _lib.BAD_ARG
 

@@ -433,12 +433,12 @@ def report_serving(seconds):
 
 
 def kernel_hash():
-    """Hash of the kernel sources, to tie stored counter readings to the code
-    they were taken on."""
+    """Hash of the sources of the single-buffer kernels (the dominant kernels of
+    the step), to tie stored counter readings to the code they were taken on."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("b64_device.hpp", "b64_codec.hip"):
+    for f in ("b64_modes.hpp", "b64_device.hpp", "b64_single.hip"):
         p = os.path.join(ROOT, "paper_1704_00605_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())

@@ -1,261 +1,28 @@
-// gfx950 kernels and the C-ABI of the base64 codec (see include/b64.h).
+// gfx950 kernels of the batched codec and their C-ABI (include/b64.h).
 //
-// Kernels:
-//   k_enc_single / k_dec_single   one buffer, grid-stride over 12-byte /
-//                                 16-character units, one unit per lane.
-//   k_plan_reduce / k_plan_scan   device planning for batches: per-message
-//                                 unit counts -> exclusive scan (unit_off),
-//                                 output-length and error-slot init.
-//   k_enc_batch / k_dec_batch     persistent batched codec: every wave owns a
-//                                 contiguous range of 64-unit groups of the
-//                                 flattened unit space of all messages.
+//   k_plan_reduce / k_plan_scan   device planning: per-message unit counts ->
+//                                 exclusive scan (unit_off), output-length
+//                                 and error-slot init.
+//   k_enc_batch_t / k_dec_batch_t persistent codec, tile layout: tiles of
+//                                 the flattened unit space of all messages,
+//                                 grid-stride.
+//   k_enc_batch_w / k_dec_batch_w persistent codec, wave layout: one
+//                                 contiguous range of 64-unit groups per wave.
 //   k_dec_batch_final             per-message verdicts.
 //   k_out_offsets                 exclusive scan of output sizes.
-//
-// Decode errors: a lane whose unit holds a non-symbol computes the exact
-// index; a wave ballot elects the first erring lane, which performs one
-// atomicMin on the 64-bit error slot (Section 2: the decoder must report
-// characters outside the alphabet; the smallest index is the one reported).
 #include <hip/hip_runtime.h>
 
-#include <stdarg.h>
-#include <stdio.h>
-#include <string.h>
-
 #include <algorithm>
-#include <atomic>
-#include <mutex>
-#include <string>
 #include <vector>
 
 #include "b64.h"
 #include "b64_device.hpp"
+#include "b64_internal.hpp"
 
 using namespace b64dev;
 
-__constant__ Tables c_tab = make_tables();
+static __constant__ Tables c_tab = make_tables();
 
-// ----------------------------------------------------------- error state --
-static thread_local std::string t_err = "no error";
-
-static int fail(int code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    t_err = buf;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(B64_HIP_ERROR, "%s failed: %s", #expr, hipGetErrorString(e_));       \
-    } while (0)
-
-// Checks that a kernel launch was accepted.
-#define LAUNCH_TRY()                                                                         \
-    do {                                                                                     \
-        hipError_t e_ = hipGetLastError();                                                   \
-        if (e_ != hipSuccess)                                                                \
-            return fail(B64_HIP_ERROR, "kernel launch failed: %s", hipGetErrorString(e_));   \
-    } while (0)
-
-// ------------------------------------------------------------ LDS tables --
-// Copies `bytes` (multiple of 4) of the constant tables into LDS.
-__device__ __forceinline__ void lds_fill(uint32_t *dst, const uint8_t *src, int bytes)
-{
-    const uint32_t *s = (const uint32_t *)src;
-    for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) dst[i] = s[i];
-}
-
-struct __attribute__((aligned(4))) u32x3 { uint32_t x, y, z; };
-struct __attribute__((aligned(4))) u32x4 { uint32_t x, y, z, w; };
-
-// ======================================================= single buffer ==
-
-// One grid-stride step of the single-buffer encode: this lane's units are
-// first + k * stride for k < UPL. Without GUARD every unit is known to be in
-// range, so all UPL loads are issued before any is consumed.
-template <bool ALIGNED, int UPL, bool GUARD>
-__device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
-                                         int64_t first, int stride, int64_t units, const uint8_t *tab)
-{
-    uint32_t w[UPL][3];
-#pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const int64_t u = first + (int64_t)k * stride;
-        if (!GUARD || u < units) {
-            if (ALIGNED) {
-                const u32x3 v = *(const u32x3 *)(src + 12 * u);
-                w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z;
-            } else {
-                load12(src + 12 * u, w[k][0], w[k][1], w[k][2]);
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const int64_t u = first + (int64_t)k * stride;
-        if (!GUARD || u < units) {
-            uint32_t o[4];
-            enc_unit(w[k][0], w[k][1], w[k][2], tab, o[0], o[1], o[2], o[3]);
-            if (ALIGNED) {
-                uint32_t *d = (uint32_t *)(dst + 16 * u);
-                __builtin_nontemporal_store(o[0], d + 0);
-                __builtin_nontemporal_store(o[1], d + 1);
-                __builtin_nontemporal_store(o[2], d + 2);
-                __builtin_nontemporal_store(o[3], d + 3);
-            } else {
-                store_words<4>(dst + 16 * u, o);
-            }
-        }
-    }
-}
-
-// Encode src[0, n): full units [0, n / 12) in a grid-stride loop over tiles
-// of blockDim * UPL units, then the final partial unit (Algorithm 1's tail)
-// by one lane.
-template <bool ALIGNED, int UPL>
-__global__ __launch_bounds__(1024) void k_enc_single(const uint8_t *__restrict__ src, int64_t n,
-                                                     uint8_t *__restrict__ dst, int mode)
-{
-    __shared__ uint32_t s_tab[16];
-    lds_fill(s_tab, c_tab.enc[mode & M_URL], 64);
-    __syncthreads();
-    const uint8_t *tab = (const uint8_t *)s_tab;
-
-    const int64_t units = n / 12;
-    const int64_t tile = (int64_t)blockDim.x * UPL;
-    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < units; t0 += (int64_t)gridDim.x * tile) {
-        if (t0 + tile <= units)
-            enc_step<ALIGNED, UPL, false>(src, dst, t0 + threadIdx.x, blockDim.x, units, tab);
-        else
-            enc_step<ALIGNED, UPL, true>(src, dst, t0 + threadIdx.x, blockDim.x, units, tab);
-    }
-    const int r = (int)(n - 12 * units);
-    if (r && blockIdx.x == 0 && threadIdx.x == 0)
-        enc_tail(src + 12 * units, r, dst + 16 * units, tab, mode & M_NOPAD);
-}
-
-// One grid-stride step of the single-buffer decode (see enc_step). Lanes of a
-// wave hold consecutive units, so the lowest erring lane of a ballot has the
-// wave's smallest offset; it alone performs the atomicMin.
-template <bool ALIGNED, int UPL, bool GUARD>
-__device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
-                                         int64_t first, int stride, int64_t L, const uint8_t *tab,
-                                         unsigned long long *err_slot)
-{
-    uint32_t w[UPL][4];
-#pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const int64_t u = first + (int64_t)k * stride;
-        if (!GUARD || u < L) {
-            if (ALIGNED) {
-                const u32x4 v = *(const u32x4 *)(src + 16 * u);
-                w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z; w[k][3] = v.w;
-            } else {
-                load16(src + 16 * u, w[k][0], w[k][1], w[k][2], w[k][3]);
-            }
-        }
-    }
-    uint32_t bad_any = 0;
-    uint32_t bad[UPL];
-#pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const int64_t u = first + (int64_t)k * stride;
-        bad[k] = 0;
-        if (!GUARD || u < L) {
-            uint32_t o[3];
-            bad[k] = dec_unit(w[k][0], w[k][1], w[k][2], w[k][3], tab, o[0], o[1], o[2]);
-            bad_any |= bad[k];
-            if (ALIGNED) {
-                uint32_t *d = (uint32_t *)(dst + 12 * u);
-                __builtin_nontemporal_store(o[0], d + 0);
-                __builtin_nontemporal_store(o[1], d + 1);
-                __builtin_nontemporal_store(o[2], d + 2);
-            } else {
-                store_words<3>(dst + 12 * u, o);
-            }
-        }
-    }
-    // rare path: some unit of this step holds a non-symbol
-    if (__ballot(bad_any & INVALID)) {
-#pragma unroll
-        for (int k = 0; k < UPL; k++) {
-            const int64_t u = first + (int64_t)k * stride;
-            const bool err = (bad[k] & INVALID) != 0;
-            const unsigned long long ball = __ballot(err);
-            if (ball && __lane_id() == __ffsll((long long)ball) - 1) {
-                const int64_t pos = 16 * u + dec_first_bad(w[k][0], w[k][1], w[k][2], w[k][3], tab);
-                atomicMin(err_slot, (unsigned long long)pos);
-            }
-        }
-    }
-}
-
-// Decode src[0, n), n >= 1. Interior units [0, L) with L = (n - 1) / 16 hold
-// 16 characters that are all before the final one; unit L (1..16 characters)
-// carries the padding and length rules. err_slot must hold ERR_NONE at
-// launch; it ends holding the smallest offending index (or ERR_NONE). The
-// lane of the final unit writes the decoded length to *len_slot when that
-// unit is valid. k_dec_final turns the pair into the verdict.
-template <bool ALIGNED, int UPL>
-__global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__ src, int64_t n,
-                                                     uint8_t *__restrict__ dst, int mode,
-                                                     unsigned long long *err_slot, int64_t *len_slot)
-{
-    __shared__ uint32_t s_tab[64];
-    lds_fill(s_tab, c_tab.dec[mode & M_URL], 256);
-    __syncthreads();
-    const uint8_t *tab = (const uint8_t *)s_tab;
-
-    const int64_t L = (n - 1) / 16;
-    const int64_t tile = (int64_t)blockDim.x * UPL;
-    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < L; t0 += (int64_t)gridDim.x * tile) {
-        if (t0 + tile <= L)
-            dec_step<ALIGNED, UPL, false>(src, dst, t0 + threadIdx.x, blockDim.x, L, tab, err_slot);
-        else
-            dec_step<ALIGNED, UPL, true>(src, dst, t0 + threadIdx.x, blockDim.x, L, tab, err_slot);
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        int nout;
-        const int r = (int)(n - 16 * L);
-        const int idx = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode, &nout);
-        if (idx >= 0) atomicMin(err_slot, (unsigned long long)(16 * L + idx));
-        else *len_slot = 12 * L + nout;
-    }
-}
-
-// Verdict of a single-buffer decode, run after k_dec_single on the same
-// stream: (length, -1) or (-1, first offending index). With reset, the error
-// slot is restored to ERR_NONE for the next call.
-__global__ void k_dec_final(unsigned long long *err_slot, const int64_t *len_slot, int64_t *out_len,
-                            int64_t *out_err, int reset)
-{
-    if (threadIdx.x == 0) {
-        const unsigned long long e = *err_slot;
-        const int64_t len = *len_slot;
-        if (e == ERR_NONE) { *out_len = len; *out_err = -1; }
-        else { *out_len = -1; *out_err = (int64_t)e; }
-        if (reset) *err_slot = ERR_NONE;
-    }
-}
-
-// Prepares an asynchronous decode's device slots: the error slot (which is
-// d_err itself) to ERR_NONE, or the final verdict of an empty input.
-__global__ void k_slots_init(int64_t *d_len, int64_t *d_err, int empty)
-{
-    if (threadIdx.x == 0) {
-        *d_len = 0;
-        *d_err = empty ? -1 : (int64_t)ERR_NONE;
-    }
-}
-
-// ============================================================== batches ==
 constexpr int PLAN_BLOCK = 256;
 constexpr int PLAN_PER_THREAD = 8;
 constexpr int PLAN_CHUNK = PLAN_BLOCK * PLAN_PER_THREAD;
@@ -805,304 +572,11 @@ __global__ __launch_bounds__(1024) void k_out_offsets(int dir, Msgs msgs, int64_
 }
 
 // ================================================================= host ==
-namespace {
-
-struct DevCache {
-    int cus = 0;
-};
-
-std::mutex g_mu;
-std::vector<DevCache> g_dev;
-
-int device_cus(int *out)
-{
-    int dev;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail(B64_HIP_ERROR, "hipGetDevice: %s", hipGetErrorString(e));
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
-    if (!g_dev[dev].cus) {
-        int c = 0;
-        e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return fail(B64_HIP_ERROR, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
-        g_dev[dev].cus = c;
-    }
-    *out = g_dev[dev].cus;
-    return B64_OK;
-}
-
-// Launch shapes of the single-buffer kernels (settable for tuning sweeps).
-// Default: 512 lanes x 2 units per workgroup and one workgroup per tile
-// (blocks_per_cu == 0), the fastest shape of a sweep over block {256, 512,
-// 1024} x units {1, 2, 4, 8} x grid {2..64 per CU, one-shot} on MI355X for
-// both directions at 1 GiB.
-struct Shape {
-    std::atomic<int> block{512};
-    std::atomic<int> upl{2};
-    std::atomic<int> blocks_per_cu{0};
-};
-Shape g_single[2];
-
-// Per-thread, per-device result slots of the synchronous decode:
-// [0] error slot (u64, kept at ERR_NONE between calls), [1] length written by
-// the final unit, [2] verdict length, [3] verdict error offset.
-struct SyncSlot {
-    int dev = -1;
-    unsigned long long *d = nullptr;
-    int64_t *h = nullptr;
-};
-thread_local std::vector<SyncSlot> t_slots;
-
-int sync_slot(SyncSlot **out)
-{
-    int dev;
-    HIP_TRY(hipGetDevice(&dev));
-    for (auto &s : t_slots)
-        if (s.dev == dev) { *out = &s; return B64_OK; }
-    SyncSlot s;
-    s.dev = dev;
-    HIP_TRY(hipMalloc((void **)&s.d, 64));
-    HIP_TRY(hipHostMalloc((void **)&s.h, 16, hipHostMallocDefault));
-    unsigned long long init[4] = {ERR_NONE, 0ull, 0ull, 0ull};
-    HIP_TRY(hipMemcpy(s.d, init, sizeof init, hipMemcpyHostToDevice));
-    t_slots.push_back(s);
-    *out = &t_slots.back();
-    return B64_OK;
-}
-
-int parse_mode(int alphabet, int *mode)
-{
-    const int a = alphabet & 0xff;
-    if (a != B64_ALPHABET_STD && a != B64_ALPHABET_URL) return fail(B64_BAD_ARG, "bad alphabet %d", a);
-    if (alphabet & ~(0xff | B64_MODE_STRICT | B64_MODE_NOPAD))
-        return fail(B64_BAD_ARG, "unknown mode bits 0x%x", alphabet);
-    if ((alphabet & B64_MODE_STRICT) && (alphabet & B64_MODE_NOPAD))
-        return fail(B64_BAD_ARG, "strict and unpadded modes cannot be combined");
-    *mode = (a ? M_URL : 0) | ((alphabet & B64_MODE_STRICT) ? M_STRICT : 0) |
-            ((alphabet & B64_MODE_NOPAD) ? M_NOPAD : 0);
-    return B64_OK;
-}
-
-int single_grid(int dir, int64_t units, int *block, int *upl, int *grid)
-{
-    int cus;
-    int rc = device_cus(&cus);
-    if (rc) return rc;
-    *block = g_single[dir].block.load();
-    *upl = g_single[dir].upl.load();
-    const int64_t per = (int64_t)(*block) * (*upl);
-    int64_t tiles = (units + per - 1) / per;
-    const int bpc = g_single[dir].blocks_per_cu.load();
-    int64_t cap = bpc ? (int64_t)cus * bpc : (int64_t)INT32_MAX;
-    *grid = (int)std::max<int64_t>(1, std::min(tiles, cap));
-    return B64_OK;
-}
-
-template <bool A>
-void launch_enc_single(int upl, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
-                       int mode, hipStream_t s)
-{
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_enc_single<A, 1>), grid, block, 0, s, src, n, dst, mode); break;
-    case 2: hipLaunchKernelGGL((k_enc_single<A, 2>), grid, block, 0, s, src, n, dst, mode); break;
-    case 8: hipLaunchKernelGGL((k_enc_single<A, 8>), grid, block, 0, s, src, n, dst, mode); break;
-    default: hipLaunchKernelGGL((k_enc_single<A, 4>), grid, block, 0, s, src, n, dst, mode); break;
-    }
-}
-
-template <bool A>
-void launch_dec_single(int upl, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
-                       int mode, unsigned long long *slot, int64_t *len_slot, hipStream_t s)
-{
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_dec_single<A, 1>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    case 2: hipLaunchKernelGGL((k_dec_single<A, 2>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    case 8: hipLaunchKernelGGL((k_dec_single<A, 8>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    default: hipLaunchKernelGGL((k_dec_single<A, 4>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    }
-}
-
-bool aligned4(const void *a, const void *b)
-{
-    return (((uintptr_t)a | (uintptr_t)b) & 3) == 0;
-}
-
-int enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, hipStream_t s)
-{
-    int block, upl, grid;
-    int rc = single_grid(0, n / 12, &block, &upl, &grid);
-    if (rc) return rc;
-    if (aligned4(src, dst)) launch_enc_single<true>(upl, grid, block, src, n, dst, mode, s);
-    else launch_enc_single<false>(upl, grid, block, src, n, dst, mode, s);
-    LAUNCH_TRY();
-    return B64_OK;
-}
-
-// Enqueues the decode kernel of src[0, n) (n >= 1); the error slot must hold
-// ERR_NONE. No verdict is formed here (see k_dec_final / k_dec_batch_final).
-int enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, unsigned long long *slot,
-                   int64_t *len_slot, hipStream_t s)
-{
-    int block, upl, grid;
-    int rc = single_grid(1, (n - 1) / 16, &block, &upl, &grid);
-    if (rc) return rc;
-    if (aligned4(src, dst)) launch_dec_single<true>(upl, grid, block, src, n, dst, mode, slot, len_slot, s);
-    else launch_dec_single<false>(upl, grid, block, src, n, dst, mode, slot, len_slot, s);
-    LAUNCH_TRY();
-    return B64_OK;
-}
-
-int64_t enc_len_host(int64_t n, int mode)
-{
-    if (mode & M_NOPAD) return 4 * (n / 3) + ((n % 3) ? (n % 3) + 1 : 0);
-    return 4 * ((n + 2) / 3);
-}
-
-}  // namespace
-
-// ================================================================ C-ABI ==
 extern "C" {
-
-const char *b64_last_error(void) { return t_err.c_str(); }
-
-int b64_device_cus(void)
-{
-    int c;
-    int rc = device_cus(&c);
-    return rc ? rc : c;
-}
-
-int64_t b64_encoded_len(int64_t n)
-{
-    if (n < 0) return fail(B64_BAD_ARG, "negative length");
-    return 4 * ((n + 2) / 3);
-}
-
-int64_t b64_encoded_len_mode(int64_t n, int mode)
-{
-    int m;
-    if (n < 0) return fail(B64_BAD_ARG, "negative length");
-    int rc = parse_mode(mode, &m);
-    if (rc) return rc;
-    return enc_len_host(n, m);
-}
-
-int64_t b64_decoded_max(int64_t m)
-{
-    if (m < 0) return fail(B64_BAD_ARG, "negative length");
-    return 3 * (m / 4);
-}
-
-int64_t b64_decoded_max_mode(int64_t m, int mode)
-{
-    int md;
-    if (m < 0) return fail(B64_BAD_ARG, "negative length");
-    int rc = parse_mode(mode, &md);
-    if (rc) return rc;
-    return 3 * (m / 4) + (((md & M_NOPAD) && (m & 3) >= 2) ? (m & 3) - 1 : 0);
-}
-
-int64_t b64_encode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, void *stream)
-{
-    int mode;
-    int rc = parse_mode(alphabet, &mode);
-    if (rc) return rc;
-    if (n < 0) return fail(B64_BAD_ARG, "negative length");
-    if (n == 0) return 0;
-    if (!src || !dst) return fail(B64_BAD_ARG, "null buffer with n > 0");
-    rc = enqueue_encode(src, n, dst, mode, (hipStream_t)stream);
-    if (rc) return rc;
-    return enc_len_host(n, mode);
-}
-
-int64_t b64_encode(const uint8_t *src, int64_t n, uint8_t *dst)
-{
-    int64_t r = b64_encode_ex(src, n, dst, B64_ALPHABET_STD, nullptr);
-    if (r > 0) HIP_TRY(hipStreamSynchronize(nullptr));
-    return r;
-}
-
-int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_off, int alphabet,
-                      void *stream)
-{
-    int mode;
-    int rc = parse_mode(alphabet, &mode);
-    if (rc) return rc;
-    if (!err_off) return fail(B64_BAD_ARG, "null err_off");
-    if (n < 0) return fail(B64_BAD_ARG, "negative length");
-    *err_off = -1;
-    if (n == 0) return 0;
-    if (!src || (!dst && n >= 4)) return fail(B64_BAD_ARG, "null buffer with n > 0");
-    SyncSlot *sl;
-    rc = sync_slot(&sl);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    rc = enqueue_decode(src, n, dst, mode, sl->d, (int64_t *)(sl->d + 1), s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, sl->d, (const int64_t *)(sl->d + 1), (int64_t *)(sl->d + 2),
-                       (int64_t *)(sl->d + 3), 1);
-    LAUNCH_TRY();
-    HIP_TRY(hipMemcpyAsync(sl->h, sl->d + 2, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int64_t len = sl->h[0], err = sl->h[1];
-    if (len < 0) {
-        *err_off = err;
-        t_err = "invalid base64 input";
-        return B64_INVALID_INPUT;
-    }
-    return len;
-}
-
-int64_t b64_decode(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_off)
-{
-    return b64_decode_ex(src, n, dst, err_off, B64_ALPHABET_STD, nullptr);
-}
-
-int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, int64_t *d_len,
-                     int64_t *d_err, void *stream)
-{
-    int mode;
-    int rc = parse_mode(alphabet, &mode);
-    if (rc) return rc;
-    if (n < 0) return fail(B64_BAD_ARG, "negative length");
-    if (!d_len || !d_err) return fail(B64_BAD_ARG, "null result slot");
-    if (n > 0 && (!src || (!dst && n >= 4))) return fail(B64_BAD_ARG, "null buffer with n > 0");
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, n == 0 ? 1 : 0);
-    LAUNCH_TRY();
-    if (n == 0) return B64_OK;
-    rc = enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, d_len, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, (unsigned long long *)d_err, d_len, d_len, d_err, 0);
-    LAUNCH_TRY();
-    return B64_OK;
-}
-
-int b64_set_single_tune(int dir, const b64_tune *t)
-{
-    if (dir != 0 && dir != 1) return fail(B64_BAD_ARG, "bad direction");
-    if (!t) return fail(B64_BAD_ARG, "null tune");
-    if (t->block) {
-        if (t->block < 64 || t->block > 1024 || (t->block & 63)) return fail(B64_BAD_ARG, "bad block");
-        g_single[dir].block = t->block;
-    }
-    if (t->units_per_lane) {
-        if (t->units_per_lane != 1 && t->units_per_lane != 2 && t->units_per_lane != 4 &&
-            t->units_per_lane != 8)
-            return fail(B64_BAD_ARG, "units_per_lane must be 1, 2, 4 or 8");
-        g_single[dir].upl = t->units_per_lane;
-    }
-    if (t->grid) {
-        // blocks per CU; -1 selects one workgroup per tile
-        if (t->grid < -1 || t->grid > 4096) return fail(B64_BAD_ARG, "blocks per CU must be -1 or 1..4096");
-        g_single[dir].blocks_per_cu = t->grid < 0 ? 0 : t->grid;
-    }
-    return B64_OK;
-}
 
 int64_t b64_batch_workspace_bytes(int64_t N)
 {
-    if (N < 0) return fail(B64_BAD_ARG, "negative N");
+    if (N < 0) return b64i_fail(B64_BAD_ARG, "negative N");
     const int64_t chunks = (N + PLAN_CHUNK - 1) / PLAN_CHUNK;
     return 8 * (N + 1) + 8 * std::max<int64_t>(chunks, 1);
 }
@@ -1110,8 +584,8 @@ int64_t b64_batch_workspace_bytes(int64_t N)
 int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *out_off,
                           const uint8_t *flags, void *stream)
 {
-    if (dir != B64_DIR_ENCODE && dir != B64_DIR_DECODE) return fail(B64_BAD_ARG, "bad direction");
-    if (N < 0 || !in_off || !out_off) return fail(B64_BAD_ARG, "bad offsets arguments");
+    if (dir != B64_DIR_ENCODE && dir != B64_DIR_DECODE) return b64i_fail(B64_BAD_ARG, "bad direction");
+    if (N < 0 || !in_off || !out_off) return b64i_fail(B64_BAD_ARG, "bad offsets arguments");
     Msgs msgs{in_off, nullptr};
     hipLaunchKernelGGL(k_out_offsets, 1, 1024, 0, (hipStream_t)stream, dir, msgs, N, flags, out_off);
     LAUNCH_TRY();
@@ -1128,17 +602,17 @@ namespace {
 int batch_shape(const b64_tune *t, int *block, int *upl, int *grid, int *layout)
 {
     int cus;
-    int rc = device_cus(&cus);
+    int rc = b64i_device_cus(&cus);
     if (rc) return rc;
     *layout = t ? t->layout : 0;
     const bool tiles = *layout == 0;
     *block = (t && t->block) ? t->block : (tiles ? 512 : 256);
     *upl = (t && t->units_per_lane) ? t->units_per_lane : 2;
     *grid = (t && t->grid) ? t->grid : cus * (tiles ? 32 : 8);
-    if (*layout != 0 && *layout != 1) return fail(B64_BAD_ARG, "bad layout %d", *layout);
-    if (*block < 64 || *block > 1024 || (*block & 63)) return fail(B64_BAD_ARG, "bad block size %d", *block);
-    if (*upl != 1 && *upl != 2 && *upl != 4 && *upl != 8) return fail(B64_BAD_ARG, "bad units_per_lane %d", *upl);
-    if (*grid < 1 || *grid > (1 << 20)) return fail(B64_BAD_ARG, "bad grid %d", *grid);
+    if (*layout != 0 && *layout != 1) return b64i_fail(B64_BAD_ARG, "bad layout %d", *layout);
+    if (*block < 64 || *block > 1024 || (*block & 63)) return b64i_fail(B64_BAD_ARG, "bad block size %d", *block);
+    if (*upl != 1 && *upl != 2 && *upl != 4 && *upl != 8) return b64i_fail(B64_BAD_ARG, "bad units_per_lane %d", *upl);
+    if (*grid < 1 || *grid > (1 << 20)) return b64i_fail(B64_BAD_ARG, "bad grid %d", *grid);
     return B64_OK;
 }
 
@@ -1146,7 +620,7 @@ template <int DIR>
 int plan(Msgs msgs, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes, int64_t *out_len,
          int64_t *err_off, int64_t **unit_off, hipStream_t s)
 {
-    if (ws_bytes < b64_batch_workspace_bytes(N) || !ws) return fail(B64_BAD_ARG, "workspace too small");
+    if (ws_bytes < b64_batch_workspace_bytes(N) || !ws) return b64i_fail(B64_BAD_ARG, "workspace too small");
     const int64_t chunks = std::max<int64_t>(1, (N + PLAN_CHUNK - 1) / PLAN_CHUNK);
     *unit_off = (int64_t *)ws;
     int64_t *partial = (int64_t *)ws + (N + 1);
@@ -1204,9 +678,9 @@ int encode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
                      const uint8_t *flags, int64_t *out_len, void *ws, int64_t ws_bytes,
                      const b64_tune *tune, hipStream_t s)
 {
-    if (N < 0) return fail(B64_BAD_ARG, "negative N");
+    if (N < 0) return b64i_fail(B64_BAD_ARG, "negative N");
     if (N == 0) return B64_OK;
-    if (!src || !msgs.begin || !dst || !out_off || !out_len) return fail(B64_BAD_ARG, "null argument");
+    if (!src || !msgs.begin || !dst || !out_off || !out_len) return b64i_fail(B64_BAD_ARG, "null argument");
     int block, upl, grid, layout;
     int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
@@ -1220,9 +694,9 @@ int decode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
                      const uint8_t *flags, int64_t *out_len, int64_t *err_off, void *ws,
                      int64_t ws_bytes, const b64_tune *tune, hipStream_t s)
 {
-    if (N < 0) return fail(B64_BAD_ARG, "negative N");
+    if (N < 0) return b64i_fail(B64_BAD_ARG, "negative N");
     if (N == 0) return B64_OK;
-    if (!src || !msgs.begin || !dst || !out_off || !out_len || !err_off) return fail(B64_BAD_ARG, "null argument");
+    if (!src || !msgs.begin || !dst || !out_off || !out_len || !err_off) return b64i_fail(B64_BAD_ARG, "null argument");
     int block, upl, grid, layout;
     int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
@@ -1256,8 +730,6 @@ int b64i_decode_planned(const uint8_t *src, const int64_t *in_begin, const int64
                             err_off, tune, s);
 }
 
-int b64i_fail(int code, const char *msg) { return fail(code, "%s", msg); }
-
 extern "C" {
 
 int b64_encode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
@@ -1282,7 +754,7 @@ int b64_encode_batch_gather(const uint8_t *src, const int64_t *in_begin, const i
                             int64_t *out_len, void *workspace, int64_t workspace_bytes,
                             const b64_tune *tune, void *stream)
 {
-    if (N > 0 && !in_len) return fail(B64_BAD_ARG, "null in_len");
+    if (N > 0 && !in_len) return b64i_fail(B64_BAD_ARG, "null in_len");
     return encode_batch_any(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, out_len, workspace,
                             workspace_bytes, tune, (hipStream_t)stream);
 }
@@ -1292,7 +764,7 @@ int b64_decode_batch_gather(const uint8_t *src, const int64_t *in_begin, const i
                             int64_t *out_len, int64_t *err_off, void *workspace,
                             int64_t workspace_bytes, const b64_tune *tune, void *stream)
 {
-    if (N > 0 && !in_len) return fail(B64_BAD_ARG, "null in_len");
+    if (N > 0 && !in_len) return b64i_fail(B64_BAD_ARG, "null in_len");
     return decode_batch_any(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, out_len, err_off,
                             workspace, workspace_bytes, tune, (hipStream_t)stream);
 }
@@ -1300,16 +772,16 @@ int b64_decode_batch_gather(const uint8_t *src, const int64_t *in_begin, const i
 int b64_encode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,
                     const int64_t *h_out_off, const uint8_t *h_flags, int64_t *out_len, void *stream)
 {
-    if (N < 0 || !h_in_off || !h_out_off) return fail(B64_BAD_ARG, "bad arguments");
+    if (N < 0 || !h_in_off || !h_out_off) return b64i_fail(B64_BAD_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int64_t> lens(N);
     for (int64_t i = 0; i < N; i++) {
         const int64_t n = h_in_off[i + 1] - h_in_off[i];
         const int fl = h_flags ? h_flags[i] : 0;
         const int mode = (fl & M_URL) | (fl & M_NOPAD);
-        lens[i] = enc_len_host(n, mode);
+        lens[i] = b64i_enc_len(n, mode);
         if (n > 0) {
-            int rc = enqueue_encode(src + h_in_off[i], n, dst + h_out_off[i], mode, s);
+            int rc = b64i_enqueue_encode(src + h_in_off[i], n, dst + h_out_off[i], mode, s);
             if (rc) return rc;
         }
     }
@@ -1330,7 +802,7 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
                     const int64_t *h_out_off, const uint8_t *h_flags, int64_t *out_len,
                     int64_t *err_off, void *stream)
 {
-    if (N < 0 || !h_in_off || !h_out_off || !out_len || !err_off) return fail(B64_BAD_ARG, "bad arguments");
+    if (N < 0 || !h_in_off || !h_out_off || !out_len || !err_off) return b64i_fail(B64_BAD_ARG, "bad arguments");
     if (N == 0) return B64_OK;
     hipStream_t s = (hipStream_t)stream;
     const int fb = (int)std::min<int64_t>((N + 255) / 256, 1024);
@@ -1340,7 +812,7 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
         const int64_t n = h_in_off[i + 1] - h_in_off[i];
         const int fl = h_flags ? h_flags[i] : 0;
         if (n == 0) continue;  // verdict (0, -1) comes from the init and final passes
-        int rc = enqueue_decode(src + h_in_off[i], n, dst + h_out_off[i], fl & 7,
+        int rc = b64i_enqueue_decode(src + h_in_off[i], n, dst + h_out_off[i], fl & 7,
                                 (unsigned long long *)(err_off + i), out_len + i, s);
         if (rc) return rc;
     }

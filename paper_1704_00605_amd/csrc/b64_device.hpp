@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "b64_modes.hpp"
+
 namespace b64dev {
 
 // ---------------------------------------------------------------- tables --
@@ -43,9 +45,9 @@ constexpr uint8_t INVALID = 0x80;
 constexpr unsigned long long ERR_NONE = 0x7fffffffffffffffull;
 
 // Mode bits (per call or per message).
-constexpr int M_URL = 1;
-constexpr int M_STRICT = 2;
-constexpr int M_NOPAD = 4;
+constexpr int M_URL = B64I_M_URL;
+constexpr int M_STRICT = B64I_M_STRICT;
+constexpr int M_NOPAD = B64I_M_NOPAD;
 
 // -------------------------------------------------------------- byte ops --
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
@@ -260,6 +262,112 @@ __device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
     for (int k = 1; k < K; k++) d[k] = alignb(o[k], o[k - 1], sh);
     // tail: low s bytes of d[K] get the last s bytes of o[K-1]
     store_edge_lo((uint8_t *)(d + K), o[K - 1] >> (8 * sh), s);
+}
+
+// ------------------------------------------------------ buffer steps --
+// Copies `bytes` (multiple of 4) of the constant tables into LDS.
+__device__ __forceinline__ void lds_fill(uint32_t *dst, const uint8_t *src, int bytes)
+{
+    const uint32_t *s = (const uint32_t *)src;
+    for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) dst[i] = s[i];
+}
+
+struct __attribute__((aligned(4))) u32x3 { uint32_t x, y, z; };
+struct __attribute__((aligned(4))) u32x4 { uint32_t x, y, z, w; };
+
+// One grid-stride step of the encode over one buffer: this lane's units are
+// first + k * stride for k < UPL. Without GUARD every unit is known to be in
+// range, so all UPL loads are issued before any is consumed.
+template <bool ALIGNED, int UPL, bool GUARD>
+__device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                         int64_t first, int stride, int64_t units, const uint8_t *tab)
+{
+    uint32_t w[UPL][3];
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const int64_t u = first + (int64_t)k * stride;
+        if (!GUARD || u < units) {
+            if (ALIGNED) {
+                const u32x3 v = *(const u32x3 *)(src + 12 * u);
+                w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z;
+            } else {
+                load12(src + 12 * u, w[k][0], w[k][1], w[k][2]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const int64_t u = first + (int64_t)k * stride;
+        if (!GUARD || u < units) {
+            uint32_t o[4];
+            enc_unit(w[k][0], w[k][1], w[k][2], tab, o[0], o[1], o[2], o[3]);
+            if (ALIGNED) {
+                uint32_t *d = (uint32_t *)(dst + 16 * u);
+                __builtin_nontemporal_store(o[0], d + 0);
+                __builtin_nontemporal_store(o[1], d + 1);
+                __builtin_nontemporal_store(o[2], d + 2);
+                __builtin_nontemporal_store(o[3], d + 3);
+            } else {
+                store_words<4>(dst + 16 * u, o);
+            }
+        }
+    }
+}
+
+// One grid-stride step of the decode over one buffer (see enc_step). Lanes of a
+// wave hold consecutive units, so the lowest erring lane of a ballot has the
+// wave's smallest offset; it alone performs the atomicMin.
+template <bool ALIGNED, int UPL, bool GUARD>
+__device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                         int64_t first, int stride, int64_t L, const uint8_t *tab,
+                                         unsigned long long *err_slot)
+{
+    uint32_t w[UPL][4];
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const int64_t u = first + (int64_t)k * stride;
+        if (!GUARD || u < L) {
+            if (ALIGNED) {
+                const u32x4 v = *(const u32x4 *)(src + 16 * u);
+                w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z; w[k][3] = v.w;
+            } else {
+                load16(src + 16 * u, w[k][0], w[k][1], w[k][2], w[k][3]);
+            }
+        }
+    }
+    uint32_t bad_any = 0;
+    uint32_t bad[UPL];
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const int64_t u = first + (int64_t)k * stride;
+        bad[k] = 0;
+        if (!GUARD || u < L) {
+            uint32_t o[3];
+            bad[k] = dec_unit(w[k][0], w[k][1], w[k][2], w[k][3], tab, o[0], o[1], o[2]);
+            bad_any |= bad[k];
+            if (ALIGNED) {
+                uint32_t *d = (uint32_t *)(dst + 12 * u);
+                __builtin_nontemporal_store(o[0], d + 0);
+                __builtin_nontemporal_store(o[1], d + 1);
+                __builtin_nontemporal_store(o[2], d + 2);
+            } else {
+                store_words<3>(dst + 12 * u, o);
+            }
+        }
+    }
+    // rare path: some unit of this step holds a non-symbol
+    if (__ballot(bad_any & INVALID)) {
+#pragma unroll
+        for (int k = 0; k < UPL; k++) {
+            const int64_t u = first + (int64_t)k * stride;
+            const bool err = (bad[k] & INVALID) != 0;
+            const unsigned long long ball = __ballot(err);
+            if (ball && __lane_id() == __ffsll((long long)ball) - 1) {
+                const int64_t pos = 16 * u + dec_first_bad(w[k][0], w[k][1], w[k][2], w[k][3], tab);
+                atomicMin(err_slot, (unsigned long long)pos);
+            }
+        }
+    }
 }
 
 }  // namespace b64dev

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "b64.h"
+#include "b64_modes.hpp"
 
 // Error slot value meaning "no error yet" (see b64_device.hpp).
 constexpr int64_t B64I_ERR_NONE = 0x7fffffffffffffffll;
@@ -21,5 +22,36 @@ int b64i_decode_planned(const uint8_t *src, const int64_t *in_begin, const int64
                         const int64_t *unit_off, int64_t *out_len, int64_t *err_off,
                         const b64_tune *tune, hipStream_t s);
 
-// Records a failure message for b64_last_error() on this thread.
-int b64i_fail(int code, const char *msg);
+// Records a failure message for b64_last_error() on this thread; returns code.
+int b64i_fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// Compute units of the current device (cached per device).
+int b64i_device_cus(int *out);
+
+// Alphabet/mode argument of the C-ABI -> B64I_M_* bits (B64_BAD_ARG if invalid).
+int b64i_parse_mode(int alphabet, int *mode);
+
+// Encoded length of n bytes under mode bits (with or without padding).
+int64_t b64i_enc_len(int64_t n, int mode);
+
+// Single-buffer launches (enqueue only). Decode needs n >= 1, *err_slot ==
+// ERR_NONE before the kernel; the final unit's lane writes *len_slot when
+// valid, and no verdict is formed.
+int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, hipStream_t s);
+int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, unsigned long long *err_slot,
+                        int64_t *len_slot, hipStream_t s);
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return b64i_fail(B64_HIP_ERROR, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+// Checks that a kernel launch was accepted.
+#define LAUNCH_TRY()                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess)                                                                \
+            return b64i_fail(B64_HIP_ERROR, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)

@@ -23,9 +23,7 @@ namespace {
 
 int hip_fail(hipError_t e, const char *what)
 {
-    char buf[256];
-    snprintf(buf, sizeof buf, "%s failed: %s", what, hipGetErrorString(e));
-    return b64i_fail(B64_HIP_ERROR, buf);
+    return b64i_fail(B64_HIP_ERROR, "%s failed: %s", what, hipGetErrorString(e));
 }
 
 #define RT_TRY(expr)                                   \

@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--only", default="",
                     help="comma list of extra reports to run: config1,batched3,batched4,serving")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-per-message", action="store_true",
+                    help="skip the per-message-launch baseline of the batched reports (for kernel traces)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain int32 copy kernel (1 GiB in, 1 GiB out) three times; "
                          "its HBM counter readings scale the codec's counter readings")
@@ -66,39 +68,60 @@ def calibrate_copy():
                       "launches": 3}), flush=True)
 
 
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(payload, text, sample_mib):
-    """The oracle (plain scalar C, all host threads) on a bounded sample."""
+    """The oracle (plain scalar C) on a bounded sample: all host threads over
+    the first sample_mib MiB, and one thread over the first 128 MiB. Same step
+    shape as the GPU step (encode n, decode m twice); median of >= 5 reps."""
     import oracle
 
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+    def measure(nb, th, min_reps, budget_s):
+        x = payload[:nb]
+        t = text[: (nb // 3) * 4]
+        te, td = [], []
+        t_start = time.perf_counter()
+        while len(te) < min_reps or (time.perf_counter() - t_start < budget_s and len(te) < 20):
+            t0 = time.perf_counter()
+            e = oracle.encode(x, threads=th)
+            t1 = time.perf_counter()
+            n, err, _ = oracle.decode(t, threads=th)
+            t2 = time.perf_counter()
+            assert err == -1 and n == nb and np.array_equal(e, t)
+            te.append(t1 - t0)
+            td.append(t2 - t1)
+        return nb, t.size, float(np.median(te)), float(np.median(td)), float(min(te)), float(min(td)), len(te)
+
     nb = min(payload.size, (sample_mib << 20) // 3 * 3)
-    x = payload[:nb]
-    t = text[: (nb // 3) * 4]
-    best_e = best_d = None
-    reps = 0
-    t_start = time.perf_counter()
-    while reps < 3 or (time.perf_counter() - t_start < 10 and reps < 20):
-        t0 = time.perf_counter()
-        e = oracle.encode(x, threads=threads)
-        t1 = time.perf_counter()
-        n, err, y = oracle.decode(t, threads=threads)
-        t2 = time.perf_counter()
-        assert err == -1 and n == nb and np.array_equal(e, t)
-        best_e = min(best_e or 1e9, t1 - t0)
-        best_d = min(best_d or 1e9, t2 - t1)
-        reps += 1
-    # same step shape as the GPU: encode n, decode m, decode m
-    step_bytes = nb + 2 * t.size
-    step_s = best_e + 2 * best_d
+    nb, nt, me, md, be, bd, reps = measure(nb, threads, 5, 8.0)
+    n1 = min(payload.size, (128 << 20) // 3 * 3)
+    n1, nt1, me1, md1, _, _, reps1 = measure(n1, 1, 5, 0.0)
+    step_bytes = nb + 2 * nt
     return {
-        "value": round(step_bytes / step_s / 1e9, 3),
+        "value": round(step_bytes / (me + 2 * md) / 1e9, 3),
         "unit": "GB/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"first {nb} bytes of the payload and their {t.size} characters; "
-                  f"best of {reps} reps of encode + 2x decode ({threads} threads, plain C -O2)",
-        "encode_GBps": round(nb / best_e / 1e9, 3),
-        "decode_GBps": round(t.size / best_d / 1e9, 3),
+        "sample": f"first {nb} bytes of the 1 GiB payload and their {nt} characters, encode + 2x decode "
+                  f"(the GPU step's shape), median of {reps} reps on {threads} threads; one-thread figures "
+                  f"over the first {n1} bytes, median of {reps1} reps; plain C -O2",
+        "cpu_model": _cpu_model(),
+        "encode_GBps": round(nb / me / 1e9, 3),
+        "decode_GBps": round(nt / md / 1e9, 3),
+        "encode_GBps_best": round(nb / be / 1e9, 3),
+        "decode_GBps_best": round(nt / bd / 1e9, 3),
+        "one_thread": {"value": round((n1 + 2 * nt1) / (me1 + 2 * md1) / 1e9, 3),
+                       "encode_GBps": round(n1 / me1 / 1e9, 3), "decode_GBps": round(nt1 / md1 / 1e9, 3)},
     }
 
 
@@ -168,9 +191,10 @@ def main():
         print(f"VERIFICATION FAILED: decode={r} corrupted={rb} expected pos {pos}", file=sys.stderr)
         sys.exit(1)
 
-    enc_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    dec_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    decb_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    enc_t = [e[0].elapsed_time(e[1]) for e in evs]
+    dec_t = [e[1].elapsed_time(e[2]) for e in evs]
+    decb_t = [e[2].elapsed_time(e[3]) for e in evs]
+    enc_ms, dec_ms, decb_ms = (float(np.mean(v)) for v in (enc_t, dec_t, decb_t))
     step_ms = wall * 1e3 / args.steps
     algo_bytes = n + m  # same for both directions: read input, write output
     enc_bw = algo_bytes / (enc_ms * 1e-3) / 1e9
@@ -215,9 +239,11 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": algo_bytes,
         },
-        "encode": {"ms": round(enc_ms, 4), "input_GBps": round(n / enc_ms / 1e6, 1),
+        "encode": {"ms": round(enc_ms, 4), "median_ms": round(float(np.median(enc_t)), 4),
+                   "min_ms": round(min(enc_t), 4), "input_GBps": round(n / enc_ms / 1e6, 1),
                    "hbm_GBps": round(enc_bw, 1), "hbm_frac": round(enc_bw / HBM_PEAK_GBPS, 4)},
-        "decode": {"ms": round(dec_ms, 4), "input_GBps": round(m / dec_ms / 1e6, 1),
+        "decode": {"ms": round(dec_ms, 4), "median_ms": round(float(np.median(dec_t)), 4),
+                   "min_ms": round(min(dec_t), 4), "input_GBps": round(m / dec_ms / 1e6, 1),
                    "hbm_GBps": round(dec_bw, 1), "hbm_frac": round(dec_bw / HBM_PEAK_GBPS, 4)},
         "decode_invalid": {"ms": round(decb_ms, 4), "err_off": pos},
         "paper_context": "AVX2 on i7-6700 (Skylake, 3.4 GHz, 1 core): ~0.25 cycles/byte "
@@ -233,11 +259,11 @@ def main():
             line["config1_latency"] = report_config1()
         if "batched3" in wanted:
             progress("config 3 batched vs per-message")
-            line["batched_config3"] = report_batched(3)
+            line["batched_config3"] = report_batched(3, not args.no_per_message)
             torch.cuda.empty_cache()
         if "batched4" in wanted:
             progress("config 4 batched vs per-message (autotuned)")
-            line["batched_config4"] = report_batched(4)
+            line["batched_config4"] = report_batched(4, not args.no_per_message)
             torch.cuda.empty_cache()
         if "serving" in wanted:
             progress("config 5 serving")
@@ -308,7 +334,7 @@ def report_config1():
     }
 
 
-def report_batched(which):
+def report_batched(which, per_message=True):
     """Configs 3/4: one persistent launch per direction over the packed batch
     (plan + codec kernels, eager and as a HIP graph, default and autotuned
     launch shape) against one single-buffer launch per message."""
@@ -375,25 +401,29 @@ def report_batched(which):
         b_len = out_len.cpu().numpy().copy()
         b_err = err.cpu().numpy().copy() if direction == codec.DIR_DECODE else None
         oo_h = out_off.cpu().numpy()
-        dst2 = torch.empty_like(dst)
-        ol2 = torch.empty(N, dtype=torch.int64, device=dev)
-        er2 = torch.empty(N, dtype=torch.int64, device=dev)
-        if direction == codec.DIR_ENCODE:
-            each = lambda: codec.encode_each(bsrc, boff_h, oo_h, dst2, ol2, h_flags=flags_h)
-        else:
-            each = lambda: codec.decode_each(bsrc, boff_h, oo_h, dst2, ol2, er2, h_flags=flags_h)
-        each_wall = _wall_ms(each, 2)
-        same = bool(np.array_equal(ol2.cpu().numpy(), b_len))
-        if direction == codec.DIR_DECODE:
-            same = same and bool(np.array_equal(er2.cpu().numpy(), b_err))
-        else:
-            same = same and bool(torch.equal(dst2, dst))
+        each_wall, same = None, None
+        if per_message:
+            dst2 = torch.empty_like(dst)
+            ol2 = torch.empty(N, dtype=torch.int64, device=dev)
+            er2 = torch.empty(N, dtype=torch.int64, device=dev)
+            if direction == codec.DIR_ENCODE:
+                each = lambda: codec.encode_each(bsrc, boff_h, oo_h, dst2, ol2, h_flags=flags_h)
+            else:
+                each = lambda: codec.decode_each(bsrc, boff_h, oo_h, dst2, ol2, er2, h_flags=flags_h)
+            each_wall = _wall_ms(each, 2)
+            same = bool(np.array_equal(ol2.cpu().numpy(), b_len))
+            if direction == codec.DIR_DECODE:
+                same = same and bool(np.array_equal(er2.cpu().numpy(), b_err))
+            else:
+                same = same and bool(torch.equal(dst2, dst))
+            del dst2
         algo = int(boff_h[-1] - boff_h[0]) + total
         out[label] = {
             "batched_ms": round(tuned_ms, 4), "batched_default_shape_ms": round(base_ms, 4),
             "batched_wall_ms": round(tuned_wall, 4), "graph_replay_ms": round(graph_ms, 4),
-            "graph_wall_ms": round(graph_wall, 4), "per_message_wall_ms": round(each_wall, 4),
-            "speedup_vs_per_message": round(each_wall / tuned_wall, 2),
+            "graph_wall_ms": round(graph_wall, 4),
+            "per_message_wall_ms": None if each_wall is None else round(each_wall, 4),
+            "speedup_vs_per_message": None if each_wall is None else round(each_wall / tuned_wall, 2),
             "input_GBps": round((boff_h[-1] - boff_h[0]) / tuned_ms / 1e6, 1),
             "hbm_GBps_algorithmic": round(algo / tuned_ms / 1e6, 1),
             "hbm_frac": round(algo / tuned_ms / 1e6 / HBM_PEAK_GBPS, 4),

@@ -115,6 +115,35 @@ int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, 
                      int64_t *d_err, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Whitespace-tolerant decode (Appendix B: space 0x20, line feed 0x0A and
+ * carriage return 0x0D are removed before decoding, as in MIME text broken
+ * into lines). The result is that of b64_decode_ex on the stripped text,
+ * with one difference: *err_off / *d_err is an index into the ORIGINAL
+ * input (a length error of the stripped text is reported at n). Alphabet:
+ * B64_ALPHABET_STD or B64_ALPHABET_URL, no mode bits (-2 otherwise).
+ * n < 2^38. dst needs capacity 3 * floor(n / 4) (the stripped length is not
+ * known in advance); no byte past the decoded length is written.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace (bytes) b64_decode_ws_async needs for n input bytes:
+ * about n / 256 plus 64. */
+int64_t b64_decode_ws_workspace_bytes(int64_t n);
+
+/* Asynchronous form: enqueues the decode on `stream`; the verdict lands in
+ * the device slots d_len (decoded length or -1) and d_err (-1 or the first
+ * offending original index). `workspace` (device, caller-owned, at least
+ * b64_decode_ws_workspace_bytes(n) bytes) must not be used by another call
+ * until this one completes. Returns B64_OK once enqueued. */
+int b64_decode_ws_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, int64_t *d_len,
+                        int64_t *d_err, void *workspace, int64_t workspace_bytes, void *stream);
+
+/* Synchronous form on `stream` (NULL: default stream), with a workspace the
+ * library keeps per thread and device. Returns the decoded length, or
+ * B64_INVALID_INPUT with *err_off (host) = first offending original index. */
+int64_t b64_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_off, int alphabet,
+                      void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched forms: N messages packed back to back. Message i is
  * src[in_off[i], in_off[i+1]); in_off has N+1 non-decreasing int64 entries
  * (in_off[0] may be > 0). Its output starts at dst + out_off[i].
@@ -292,6 +321,11 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
  * tile, the default). Zero fields keep the current value. Process-wide;
  * meant for tuning sweeps. */
 int b64_set_single_tune(int dir, const b64_tune *t);
+
+/* Launch shape of the whitespace-tolerant decode (tuning): block 256, 512 or
+ * 1024 threads; units_per_lane = input dwords per lane per tile (2, 4 or 8);
+ * other fields ignored; zero fields keep the current value. Process-wide. */
+int b64_set_ws_tune(const b64_tune *t);
 
 /* Thread-local description of the last failure (never NULL). */
 const char *b64_last_error(void);

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libb64hip.so")
-SOURCES = ["b64_host.cpp", "b64_single.hip", "b64_batch.hip", "b64_runtime.cpp"]
+SOURCES = ["b64_host.cpp", "b64_single.hip", "b64_batch.hip", "b64_ws.hip", "b64_runtime.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -101,12 +101,65 @@ def decode_async(src, out, result, alphabet=ALPHABET_STD, stream=None):
     receives (length | -1, -1 | first offending index)."""
     src = _dev_u8(src, "src")
     _dev_u8(out, "out")
+    if out.numel() < decoded_max(src.numel(), alphabet & ~0xff):
+        raise ValueError("out is too small")
     if result.dtype != torch.int64 or result.numel() < 2 or not result.is_cuda:
         raise TypeError("result must be an int64 CUDA tensor with 2 slots")
     rp = result.data_ptr()
     r = lib().b64_decode_async(_ptr(src), src.numel(), _ptr(out), int(alphabet),
                                ctypes.c_void_p(rp), ctypes.c_void_p(rp + 8), _stream(stream))
     check(r, "b64_decode_async")
+
+
+def ws_workspace_bytes(n):
+    return check(lib().b64_decode_ws_workspace_bytes(int(n)), "b64_decode_ws_workspace_bytes")
+
+
+def decode_ws(src, alphabet=ALPHABET_STD, out=None, stream=None):
+    """Whitespace-tolerant decode (space, LF, CR removed first). Returns
+    ``(bytes_tensor, -1)`` or ``(None, err_off)`` with the first offending
+    index in the coordinates of ``src``. Waits for ``stream``."""
+    src = _dev_u8(src, "src")
+    n = src.numel()
+    cap = 3 * (n // 4)
+    if out is None:
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=src.device)
+    else:
+        _dev_u8(out, "out")
+        if out.numel() < cap:
+            raise ValueError("out is too small")
+    err = ctypes.c_int64(-1)
+    r = lib().b64_decode_ws(_ptr(src), n, _ptr(out), ctypes.byref(err), int(alphabet), _stream(stream))
+    check(r, "b64_decode_ws")
+    if r < 0:
+        return None, err.value
+    return out[:r], -1
+
+
+def decode_ws_async(src, out, result, workspace, alphabet=ALPHABET_STD, stream=None):
+    """Non-blocking whitespace-tolerant decode; ``result`` (int64 CUDA, 2
+    slots) receives (length | -1, -1 | first offending original index).
+    ``workspace`` is a uint8 CUDA tensor of at least ws_workspace_bytes(n)."""
+    src = _dev_u8(src, "src")
+    _dev_u8(out, "out")
+    _dev_u8(workspace, "workspace")
+    n = src.numel()
+    if out.numel() < 3 * (n // 4):
+        raise ValueError("out is too small")
+    if workspace.numel() < ws_workspace_bytes(n):
+        raise ValueError("workspace is too small")
+    if result.dtype != torch.int64 or result.numel() < 2 or not result.is_cuda:
+        raise TypeError("result must be an int64 CUDA tensor with 2 slots")
+    rp = result.data_ptr()
+    r = lib().b64_decode_ws_async(_ptr(src), n, _ptr(out), int(alphabet), ctypes.c_void_p(rp),
+                                  ctypes.c_void_p(rp + 8), _ptr(workspace), workspace.numel(),
+                                  _stream(stream))
+    check(r, "b64_decode_ws_async")
+
+
+def set_ws_tune(block=0, dwords_per_lane=0):
+    t = Tune(block=block, units_per_lane=dwords_per_lane, grid=0, layout=0)
+    check(lib().b64_set_ws_tune(ctypes.byref(t)), "b64_set_ws_tune")
 
 
 def set_single_tune(direction, block=0, units_per_lane=0, blocks_per_cu=0):

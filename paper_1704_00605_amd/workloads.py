@@ -151,3 +151,53 @@ def serving_trace(rate=200_000.0, seconds=10.0, lo=64, hi=1 << 20, seed=4, corru
     ranks = rng.integers(0, 192, size=n)
     return {"t_arrival": t, "op": op, "size": size, "corrupt": corrupt,
             "corrupt_u": u, "corrupt_rank": ranks}
+
+
+# ------------------------------------------------------ whitespace layouts --
+# Text layouts for the whitespace-tolerant decode (Appendix B removes space,
+# line feed and carriage return before decoding). These only move bytes
+# around: a text is cut into lines, or whitespace bytes are inserted.
+WS_BYTES = np.frombuffer(b" \n\r", dtype=np.uint8)
+
+
+def wrap_lines(text, width=76, eol=b"\r\n"):
+    """Text cut into lines of `width` characters, each followed by `eol`
+    (MIME uses 76 and CRLF, PEM 64 and LF); the last line may be shorter and
+    also ends with `eol`. Returns (wrapped, original index of every kept
+    character)."""
+    text = np.asarray(text, dtype=np.uint8)
+    eol = np.frombuffer(eol, dtype=np.uint8)
+    m = text.size
+    lines = -(-m // width)
+    e = eol.size
+    out = np.empty(m + lines * e, dtype=np.uint8)
+    idx = np.arange(m, dtype=np.int64)
+    pos = idx + (idx // width) * e
+    out[pos] = text
+    ends = np.minimum((np.arange(lines, dtype=np.int64) + 1) * width, m)
+    starts = ends + np.arange(lines, dtype=np.int64) * e
+    for j in range(e):
+        out[starts + j] = eol[j]
+    return out, pos
+
+
+def sprinkle_ws(rng, text, density, run_max=3):
+    """Inserts, before each character independently with probability
+    `density`, a run of 1..run_max whitespace bytes drawn from WS_BYTES.
+    Returns (new text, new index of every original character)."""
+    text = np.asarray(text, dtype=np.uint8)
+    m = text.size
+    runs = np.where(rng.uniform(size=m) < density, rng.integers(1, run_max + 1, m), 0).astype(np.int64)
+    pos = np.arange(m, dtype=np.int64) + np.cumsum(runs)
+    total = m + int(runs.sum())
+    out = WS_BYTES[rng.integers(0, 3, total)]
+    out[pos] = text
+    return out, pos
+
+
+def mime_1gib(seed=5):
+    """Whitespace workload: 1 GiB of uniform random bytes (seed 5) whose
+    base64 text is cut into 76-character CRLF lines (MIME)."""
+    rng = np.random.default_rng(seed)
+    return {"payload": random_bytes(rng, 1 << 30), "width": 76, "eol": b"\r\n",
+            "corrupt_u": float(rng.uniform()), "corrupt_rank": int(rng.integers(0, 192))}

@@ -1,0 +1,188 @@
+"""Whitespace-tolerant decode (Appendix B: space, LF and CR are removed before
+decoding) on the GPU against the oracle's decode_ws, which strips, decodes
+and reports errors in the coordinates of the original input."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1704_00605_amd import codec, workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SHAPES = [(b, c) for b in (256, 512, 1024) for c in (2, 4, 8)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_ws(a, alphabet=0, shift=0):
+    """decode_ws of host bytes `a`, placed `shift` bytes into a device buffer."""
+    buf = torch.zeros(a.size + shift + 4, dtype=torch.uint8, device=DEV)
+    if a.size:
+        buf[shift:shift + a.size] = dev(a)
+    out, err = codec.decode_ws(buf[shift:shift + a.size], alphabet)
+    return (-1, err, None) if out is None else (out.numel(), -1, out.cpu().numpy())
+
+
+def check(a, alphabet=0, shift=0):
+    want = oracle.decode_ws(a, alphabet)
+    got = gpu_ws(a, alphabet, shift)
+    assert got[:2] == want[:2], (got[:2], want[:2], a.size)
+    if want[0] > 0:
+        assert np.array_equal(got[2], want[2])
+    return want
+
+
+@pytest.fixture(autouse=True)
+def default_shape():
+    yield
+    codec.set_ws_tune(512, 8)
+
+
+def test_ws_small_random_cases():
+    rng = np.random.default_rng(0)
+    for trial in range(400):
+        L = int(rng.integers(0, 400))
+        text = oracle.encode(rng.integers(0, 256, L, dtype=np.uint8))
+        a, _ = workloads.sprinkle_ws(rng, text, float(rng.choice([0, 0.05, 0.3, 0.9])))
+        if rng.uniform() < 0.3 and a.size:
+            a[rng.integers(0, a.size)] = rng.choice([ord("="), ord("#"), ord("A"), 0x80, ord("-")])
+        if rng.uniform() < 0.1 and a.size:
+            a = a[:-1]
+        check(a)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ws_multi_tile_layouts_every_shape(shape):
+    codec.set_ws_tune(*shape)
+    rng = np.random.default_rng(1)
+    x = rng.integers(0, 256, 200_003, dtype=np.uint8)
+    text = oracle.encode(x)
+    for width, eol in ((76, b"\r\n"), (64, b"\n")):
+        a, _ = workloads.wrap_lines(text, width, eol)
+        w = check(a)
+        assert w[0] == x.size and np.array_equal(w[2], x)
+    a, _ = workloads.sprinkle_ws(rng, text, 0.2, run_max=5)
+    check(a)
+
+
+def test_ws_long_whitespace_runs_across_tiles():
+    # runs longer than any tile: tiles with no kept byte, quads and padding
+    # split across such tiles
+    rng = np.random.default_rng(2)
+    for shape in ((256, 2), (1024, 8)):
+        codec.set_ws_tune(*shape)
+        for L in (1, 2, 3, 4, 5, 1000, 4099):
+            text = oracle.encode(rng.integers(0, 256, L, dtype=np.uint8))
+            parts = []
+            for i, ch in enumerate(text):
+                if rng.uniform() < 0.2:
+                    parts.append(workloads.WS_BYTES[rng.integers(0, 3, int(rng.integers(1, 20_000)))])
+                parts.append(np.array([ch], np.uint8))
+            parts.append(workloads.WS_BYTES[rng.integers(0, 3, 50_000)])
+            a = np.concatenate(parts)
+            w = check(a)
+            assert w[1] == -1
+
+
+def test_ws_all_whitespace_and_empty():
+    for n in (0, 1, 3, 4, 5000, 70_000):
+        a = workloads.WS_BYTES[np.arange(n) % 3]
+        assert gpu_ws(a)[:2] == (0, -1)
+        check(a)
+
+
+@pytest.mark.parametrize("case", [
+    b"Zg==", b"Zg=\n=", b"Zg\r\n==\r\n", b"Z g = =", b"Zg=X", b"Zg==Zg==", b"Z===", b"Zm9v\nYg",
+    b"Zm9vYg=", b"=", b"==", b"Zh==", b"Zm9v YmFy", b"Zm9v\tYmFy", b"QUJD\n\n\n\nREVG\n",
+])
+def test_ws_padding_and_length_readings(case):
+    a = np.frombuffer(case, np.uint8).copy()
+    check(a)
+
+
+def test_ws_errors_in_original_coordinates():
+    rng = np.random.default_rng(3)
+    text = oracle.encode(rng.integers(0, 256, 150_000, dtype=np.uint8))
+    a, pos = workloads.wrap_lines(text, 76, b"\r\n")
+    for trial in range(40):
+        b = a.copy()
+        j = int(rng.integers(0, text.size))
+        b[pos[j]] = workloads.corruption_byte(int(rng.integers(0, 192)), 0, j, text.size)
+        w = check(b)
+        assert w[:2] == (-1, int(pos[j]))
+    # a tab in place of a line's CR is not removed: an error at its index
+    b = a.copy()
+    b[pos[76 * 3 - 1] + 1] = ord("\t")
+    assert check(b)[:2] == (-1, int(pos[76 * 3 - 1]) + 1)
+    # two errors: the first in original order wins
+    b = a.copy()
+    b[pos[9000]] = ord("*")
+    b[pos[100]] = ord("=")
+    assert check(b)[:2] == (-1, int(pos[100]))
+
+
+def test_ws_url_alphabet_and_misaligned_buffers():
+    rng = np.random.default_rng(4)
+    x = rng.integers(0, 256, 90_001, dtype=np.uint8)
+    text = oracle.encode(x, 1)
+    a, _ = workloads.wrap_lines(text, 64, b"\n")
+    for shift in (0, 1, 2, 3):
+        w = check(a, alphabet=1, shift=shift)
+        assert np.array_equal(w[2], x)
+    b = a.copy()
+    b[10] = ord("+")  # standard-only symbol
+    check(b, alphabet=1)
+    # unaligned output view
+    out = torch.zeros(3 * (a.size // 4) + 3, dtype=torch.uint8, device=DEV)
+    got, err = codec.decode_ws(dev(a), 1, out=out[1:])
+    assert err == -1 and np.array_equal(got.cpu().numpy(), x)
+    assert out[0].item() == 0
+
+
+def test_ws_async_reuses_workspace_and_writes_nothing_past_the_length():
+    rng = np.random.default_rng(5)
+    ws = torch.empty(codec.ws_workspace_bytes(1 << 20), dtype=torch.uint8, device=DEV)
+    res = torch.zeros(2, dtype=torch.int64, device=DEV)
+    for L in (700_000, 123, 50_001, 0, 1):
+        x = rng.integers(0, 256, L, dtype=np.uint8)
+        a, _ = workloads.wrap_lines(oracle.encode(x), 76, b"\r\n")
+        out = torch.full((3 * (a.size // 4) + 64,), 0xEE, dtype=torch.uint8, device=DEV)
+        codec.decode_ws_async(dev(a), out, res, ws)
+        torch.cuda.synchronize()
+        assert res.tolist() == [L, -1]
+        o = out.cpu().numpy()
+        assert np.array_equal(o[:L], x) and (o[L:] == 0xEE).all()
+
+
+def test_ws_mime_1gib_properties():
+    """Full-size MIME text (1 GiB payload, 76-character CRLF lines): the decode
+    returns the payload; with one injected byte it reports that byte's
+    original index. Both hold by construction at any size."""
+    w = workloads.mime_1gib()
+    x = torch.from_numpy(w["payload"]).to(DEV)
+    del w["payload"]
+    m = codec.encoded_len(x.numel())
+    text = codec.encode(x)
+    lines = -(-m // 76)
+    wrapped = torch.empty(m + 2 * lines, dtype=torch.uint8, device=DEV)
+    full = m // 76
+    v = wrapped[: full * 78].view(full, 78)
+    v[:, :76] = text[: full * 76].view(full, 76)
+    v[:, 76] = 13
+    v[:, 77] = 10
+    rest = m - full * 76
+    if rest:
+        wrapped[full * 78: full * 78 + rest] = text[full * 76:]
+        wrapped[full * 78 + rest:] = torch.tensor([13, 10], dtype=torch.uint8, device=DEV)
+    del text
+    out, err = codec.decode_ws(wrapped)
+    assert err == -1 and out.numel() == x.numel() and torch.equal(out, x)
+    j = min(int(w["corrupt_u"] * m), m - 3)
+    p = j + 2 * (j // 76)
+    wrapped[p] = workloads.corruption_byte(w["corrupt_rank"], 0, j, m)
+    del out
+    out, err = codec.decode_ws(wrapped)
+    assert out is None and err == p

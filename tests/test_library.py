@@ -68,6 +68,14 @@ def test_argument_errors_need_no_gpu(L):
     assert L.b64_batch_workspace_bytes(100000) >= 8 * 100001
     assert L.b64_encode_batch(None, None, -1, None, None, None, None, None, 0, None, None) == _lib.BAD_ARG
     assert L.b64_encode_batch(None, None, 0, None, None, None, None, None, 0, None, None) == 0
+    assert L.b64_decode_ws_workspace_bytes(-1) == _lib.BAD_ARG
+    assert L.b64_decode_ws_workspace_bytes(1 << 30) >= 8 * ((1 << 30) // 2048)
+    assert L.b64_decode_ws(None, 0, None, ctypes.byref(err), 0, None) == 0 and err.value == -1
+    assert L.b64_decode_ws(None, 4, None, ctypes.byref(err), _lib.MODE_STRICT, None) == _lib.BAD_ARG
+    assert L.b64_decode_ws(None, 1 << 38, None, ctypes.byref(err), 0, None) == _lib.BAD_ARG
+    assert L.b64_decode_ws_async(None, 8, None, 0, None, None, None, 0, None) == _lib.BAD_ARG
+    ws_bad = _lib.Tune(block=384, units_per_lane=2, grid=0, layout=0)
+    assert L.b64_set_ws_tune(ctypes.byref(ws_bad)) == _lib.BAD_ARG
     bad = _lib.Tune(block=100, units_per_lane=0, grid=0, layout=0)
     assert L.b64_set_single_tune(0, ctypes.byref(bad)) == _lib.BAD_ARG
     assert L.b64_set_single_tune(5, ctypes.byref(bad)) == _lib.BAD_ARG

@@ -1,34 +1,32 @@
 // gfx950 whitespace-tolerant decode (Appendix B: space, line feed and
-// carriage return are removed before decoding) fused into one pass, and its
-// C-ABI (include/b64.h).
+// carriage return are removed before decoding), and its C-ABI
+// (include/b64.h). The input is cut into tiles of blockDim * 4 * CPL bytes.
 //
-//   k_ws_init       clears the tile counter, the error slots and the tile
-//                   status words.
-//   k_dec_ws        one tile of the input per workgroup, tiles taken in order
-//                   from an atomic counter:
-//                     1. load dwords, classify every byte through one LDS
-//                        table (symbol value, '=', whitespace, invalid);
-//                     2. kept-byte prefix counts: per wave from ballots of the
-//                        four byte positions and mbcnt, per workgroup from the
-//                        wave totals;
-//                     3. compact the kept class bytes into LDS;
-//                     4. decoupled look-back: publish the tile's kept count
-//                        and last three kept class bytes, walk back over the
-//                        status words of earlier tiles to get the stripped
-//                        offset P of the tile's first kept byte and the kept
-//                        bytes just before it;
-//                     5. decode every quad of the stripped text that ends in
-//                        this tile (quads straddling tiles are completed from
-//                        the carried bytes) and write its bytes at 3 * quad.
-//   k_dec_ws_final  verdict from the last tile's status and the error slots.
+//   k_ws_count    per tile: number of kept (non-whitespace) bytes and the
+//                 last three of them, from SWAR whitespace tests; also resets
+//                 the error slots.
+//   k_ws_reduce   per group of 2048 tiles: the ordered combination of their
+//                 (count, last three) states.
+//   k_ws_prefix   per tile: the exclusive prefix state, i.e. the stripped
+//                 offset P of the tile's first kept byte and the three kept
+//                 bytes just before it (an ordered scan; the operator keeps
+//                 counts and the last three bytes, so it is associative).
+//   k_dec_ws      per tile: classify every byte through one LDS table
+//                 (symbol value, '=', whitespace, invalid), compact the kept
+//                 class bytes into LDS with ballot + mbcnt prefix counts, put
+//                 the carried bytes of the quad that straddles into the tile
+//                 in front, report invalid bytes and '=' in original
+//                 coordinates, and decode every quad of the stripped text that
+//                 ends in this tile (its bytes go to 3 * quad index).
+//   k_dec_ws_final verdict from the total state and the error slots.
 //
-// Errors are reported in the coordinates of the original input: a tile
-// checks its own bytes, so it knows their original indexes. A byte outside
-// the alphabet is an error wherever it is; '=' is valid only as the last one
-// or two kept bytes of a stripped text whose length is a multiple of 4, which
-// only the final verdict can tell; since stripping keeps order, the first '='
-// in stripped order is the first in original order, so two atomicMin slots
-// (original and stripped index) describe it.
+// Two passes read the input (count, then decode) and no tile waits for
+// another. A byte outside the alphabet is an error wherever it is; '=' is
+// valid only as the last one or two kept bytes of a stripped text whose
+// length is a multiple of 4, which only the final verdict can tell; since
+// stripping keeps order, the first '=' in stripped order is the first in
+// original order, so two atomicMin slots (original and stripped index)
+// describe it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,45 +69,61 @@ constexpr WsTables make_ws_tables()
 
 static __constant__ WsTables c_ws = make_ws_tables();
 
-// --------------------------------------------------------- tile status --
-// One 64-bit word per tile: flag (2 bits: 0 not ready, 1 aggregate of this
-// tile alone, 2 inclusive prefix over tiles 0..t), kept count (38 bits) and
-// the last three kept class bytes (24 bits, the most recent in the low
-// byte; fewer when the count is below 3). Counts are below 2^38.
-constexpr unsigned long long ST_AGG = 1ull << 62;
-constexpr unsigned long long ST_INC = 2ull << 62;
+// ----------------------------------------------------------- tile states --
+// State of a run of input: kept-byte count (38 bits) and its last three kept
+// bytes (24 bits, the latest in the low byte; fewer when the count is below
+// 3), packed in one 64-bit word. Counts stay below 2^38.
 constexpr int64_t WS_MAX_N = (1ll << 38) - 1;
 
-__device__ __forceinline__ unsigned long long st_make(unsigned long long flag, uint64_t cnt, uint32_t car)
-{
-    return flag | (cnt << 24) | (car & 0xffffffu);
-}
-__device__ __forceinline__ uint64_t st_cnt(unsigned long long s) { return (s >> 24) & ((1ull << 38) - 1); }
-__device__ __forceinline__ uint32_t st_car(unsigned long long s) { return (uint32_t)(s & 0xffffffu); }
+struct WsSt {
+    uint64_t c;
+    uint32_t r;
+};
 
 // Last three kept bytes of "a then b" where b holds nb kept bytes.
 __device__ __forceinline__ uint32_t car_join(uint32_t a, uint32_t b, uint64_t nb)
 {
     return nb >= 3 ? b : (((a << (8 * nb)) | b) & 0xffffffu);
 }
+// State of run a followed by run b.
+__device__ __forceinline__ WsSt st_join(WsSt a, WsSt b) { return {a.c + b.c, car_join(a.r, b.r, b.c)}; }
+__device__ __forceinline__ unsigned long long st_pack(WsSt s) { return (s.c << 24) | (s.r & 0xffffffu); }
+__device__ __forceinline__ WsSt st_unpack(unsigned long long w) { return {w >> 24, (uint32_t)(w & 0xffffffu)}; }
 
-// Slots of the workspace (64-bit words): [0] tile counter, [1] first invalid
-// byte (original index), [2] first '=' (original index), [3] first '='
-// (stripped index); the tile status words start at word 8.
-constexpr int WS_SLOT_WORDS = 8;
-
-__global__ void k_ws_init(unsigned long long *__restrict__ ws, int64_t T)
+__device__ __forceinline__ WsSt shfl_up_st(WsSt s, int d)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i0 == 0) {
-        ws[0] = 0;
-        ws[1] = ERR_NONE;
-        ws[2] = ERR_NONE;
-        ws[3] = ERR_NONE;
-    }
-    unsigned long long *st = ws + WS_SLOT_WORDS;
-    for (int64_t i = i0; i < T; i += (int64_t)gridDim.x * blockDim.x) st[i] = 0;
+    return {(uint64_t)__shfl_up((long long)s.c, d, 64), (uint32_t)__shfl_up((int)s.r, d, 64)};
 }
+
+// Ordered inclusive scan of one state per thread over the block (blockDim a
+// multiple of 64, at most 1024); *total receives the block's state.
+__device__ WsSt block_scan_st(WsSt v, WsSt *total)
+{
+    __shared__ unsigned long long s_w[16];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const WsSt o = shfl_up_st(v, d);
+        if (lane >= d) v = st_join(o, v);
+    }
+    if (lane == 63) s_w[wid] = st_pack(v);
+    __syncthreads();
+    WsSt pre{0, 0};
+    for (int i = 0; i < wid; i++) pre = st_join(pre, st_unpack(s_w[i]));
+    WsSt tot{0, 0};
+    for (int i = 0; i < nw; i++) tot = st_join(tot, st_unpack(s_w[i]));
+    __syncthreads();
+    *total = tot;
+    return st_join(pre, v);
+}
+
+// Workspace (64-bit words): [0..7] slots ([1] first invalid byte, original
+// index; [2] first '=', original index; [3] first '=', stripped index), then
+// tile states [T], tile prefixes [T], group states [G].
+constexpr int WS_SLOT_WORDS = 8;
+constexpr int WS_SCAN_BLOCK = 256;
+constexpr int WS_SCAN_PER = 8;
+constexpr int WS_GROUP = WS_SCAN_BLOCK * WS_SCAN_PER;  // tiles per scan group
 
 __device__ __forceinline__ uint32_t load4(const uint8_t *p)
 {
@@ -119,72 +133,265 @@ __device__ __forceinline__ uint32_t load4(const uint8_t *p)
     return s ? alignb(d[1], d[0], s) : d[0];
 }
 
+// 16 bytes at src + off (off a multiple of 16 from the tile base); bytes
+// past the end read as spaces (removed).
+template <bool ALIGNED>
+__device__ __forceinline__ void tile_load16(const uint8_t *__restrict__ src, int64_t n, int64_t off, uint32_t (&w)[4])
+{
+    if (off + 16 <= n) {
+        if (ALIGNED) {
+            const uint4 v = *(const uint4 *)(src + off);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+            load16(src + off, w[0], w[1], w[2], w[3]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+        uint32_t x = 0x20202020u;
+        for (int j = 0; j < 4; j++) {
+            const int64_t o = off + 4 * d + j;
+            if (o < n) x = (x & ~(0xffu << (8 * j))) | ((uint32_t)src[o] << (8 * j));
+        }
+        w[d] = x;
+    }
+}
+
+// 4-bit mask of the bytes of w that are kept: those above 0x20. On a valid
+// input every byte at or below 0x20 is space, LF or CR, so this removes
+// exactly the whitespace; on an invalid input the verdict does not depend on
+// the counts (see k_dec_ws_final), and invalid bytes are still found by
+// their class.
+__device__ __forceinline__ uint32_t kept4(uint32_t w)
+{
+    const uint32_t x = (((w & 0x7f7f7f7fu) + 0x5f5f5f5fu) | w) & 0x80808080u;  // bit 8j+7: byte j > 0x20
+    const uint32_t y = x >> 7;
+    return (y | (y >> 7) | (y >> 14) | (y >> 21)) & 0xf;
+}
+
+// Tile = BLOCK * 16 * CPL bytes; lane tid reads the 16-byte chunks
+// k * BLOCK + tid (k < CPL), so memory order is (k, wave, lane, byte).
+template <int BLOCK, int CPL, bool ALIGNED>
+__global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ src, int64_t n,
+                                                    unsigned long long *__restrict__ ws)
+{
+    constexpr int TILE = BLOCK * 16 * CPL;
+    constexpr int NW = BLOCK / 64;
+    constexpr int E = CPL * NW;
+    __shared__ uint32_t s_cnt[E], s_car[E];
+    const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+    const int64_t t = blockIdx.x;
+    if (t == 0 && tid == 0) {
+        ws[1] = ERR_NONE;
+        ws[2] = ERR_NONE;
+        ws[3] = ERR_NONE;
+    }
+    const int64_t base = t * TILE;
+    uint32_t w[CPL][4];
+#pragma unroll
+    for (int k = 0; k < CPL; k++) tile_load16<ALIGNED>(src, n, base + 16 * ((int64_t)k * BLOCK + tid), w[k]);
+#pragma unroll
+    for (int k = 0; k < CPL; k++) {
+        const uint32_t keep = kept4(w[k][0]) | (kept4(w[k][1]) << 4) | (kept4(w[k][2]) << 8) | (kept4(w[k][3]) << 12);
+        const uint32_t c = __popc(keep);
+        uint32_t tot = 0;
+#pragma unroll
+        for (int b = 0; b < 5; b++) tot += (uint32_t)__popcll(__ballot((c >> b) & 1)) << b;
+        // last three kept bytes of the wave's segment: from its last lanes
+        // that keep anything (at most three of them), in scalar registers
+        unsigned long long nz = __ballot(c > 0);
+        uint32_t ac = 0, ar = 0;
+        while (nz && ac < 3) {
+            const int h = 63 - __clzll(nz);
+            uint32_t m = __builtin_amdgcn_readlane(keep, h);
+            const uint32_t x[4] = {(uint32_t)__builtin_amdgcn_readlane(w[k][0], h),
+                                   (uint32_t)__builtin_amdgcn_readlane(w[k][1], h),
+                                   (uint32_t)__builtin_amdgcn_readlane(w[k][2], h),
+                                   (uint32_t)__builtin_amdgcn_readlane(w[k][3], h)};
+            uint32_t car = 0, nc = 0;
+            while (m && nc < 3) {
+                const int j = 31 - __clz(m);
+                car |= ((x[j >> 2] >> (8 * (j & 3))) & 0xffu) << (8 * nc);
+                m &= ~(1u << j);
+                nc++;
+            }
+            ar = car_join(car, ar, ac);
+            ac += __popc(__builtin_amdgcn_readlane(keep, h));
+            nz &= ~(1ull << h);
+        }
+        if (lane == 0) {
+            s_cnt[k * NW + wid] = tot;
+            s_car[k * NW + wid] = ar;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t cnt = 0;
+        for (int i = 0; i < E; i++) cnt += s_cnt[i];
+        uint32_t ac = 0, ar = 0;
+        for (int i = E - 1; i >= 0 && ac < 3; i--) {
+            ar = car_join(s_car[i], ar, ac);
+            ac += s_cnt[i];
+        }
+        ws[WS_SLOT_WORDS + t] = st_pack({cnt, ar});
+    }
+}
+
+// Group g: the ordered combination of tile states [g * WS_GROUP, ...).
+__global__ __launch_bounds__(WS_SCAN_BLOCK) void k_ws_reduce(unsigned long long *__restrict__ ws, int64_t T)
+{
+    const unsigned long long *st = ws + WS_SLOT_WORDS;
+    unsigned long long *grp = ws + WS_SLOT_WORDS + 2 * T;
+    const int64_t i0 = (int64_t)blockIdx.x * WS_GROUP + (int64_t)threadIdx.x * WS_SCAN_PER;
+    WsSt v{0, 0};
+    for (int i = 0; i < WS_SCAN_PER; i++)
+        if (i0 + i < T) v = st_join(v, st_unpack(st[i0 + i]));
+    WsSt tot;
+    (void)block_scan_st(v, &tot);
+    if (threadIdx.x == 0) grp[blockIdx.x] = st_pack(tot);
+}
+
+// Exclusive prefix state of every tile: groups before this block (an ordered
+// reduction over them), then the block's own ordered scan.
+__global__ __launch_bounds__(WS_SCAN_BLOCK) void k_ws_prefix(unsigned long long *__restrict__ ws, int64_t T)
+{
+    const unsigned long long *st = ws + WS_SLOT_WORDS;
+    unsigned long long *pre = ws + WS_SLOT_WORDS + T;
+    const unsigned long long *grp = ws + WS_SLOT_WORDS + 2 * T;
+    const int64_t g = blockIdx.x;
+    // groups [0, g): thread i combines a contiguous share, then the block scan
+    // orders the shares
+    const int64_t per = (g + WS_SCAN_BLOCK - 1) / WS_SCAN_BLOCK;
+    WsSt gv{0, 0};
+    for (int64_t j = (int64_t)threadIdx.x * per; j < min(g, (int64_t)(threadIdx.x + 1) * per); j++)
+        gv = st_join(gv, st_unpack(grp[j]));
+    WsSt before;
+    (void)block_scan_st(gv, &before);
+    const int64_t i0 = g * WS_GROUP + (int64_t)threadIdx.x * WS_SCAN_PER;
+    WsSt tv[WS_SCAN_PER];
+    WsSt v{0, 0};
+    for (int i = 0; i < WS_SCAN_PER; i++) {
+        tv[i] = i0 + i < T ? st_unpack(st[i0 + i]) : WsSt{0, 0};
+        v = st_join(v, tv[i]);
+    }
+    WsSt tot;
+    const WsSt inc = block_scan_st(v, &tot);
+    (void)tot;
+    // exclusive prefix of this thread's first tile: the groups before, then
+    // the inclusive scan of the previous thread
+    __shared__ unsigned long long s_last[16];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const WsSt prev = shfl_up_st(inc, 1);
+    if (lane == 63) s_last[wid] = st_pack(inc);
+    __syncthreads();
+    WsSt p{0, 0};
+    if (threadIdx.x > 0) p = lane > 0 ? prev : st_unpack(s_last[wid - 1]);
+    WsSt run = st_join(before, p);
+    for (int i = 0; i < WS_SCAN_PER; i++) {
+        if (i0 + i < T) pre[i0 + i] = st_pack(run);
+        run = st_join(run, tv[i]);
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts
+// by 1, 2, 4, 8 within each row of 16 lanes, then the last lane of a row is
+// added to the next row (row_bcast:15) and lane 31 to the upper half
+// (row_bcast:31). Lanes whose DPP source lies outside the row keep 0.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // Quad of class bytes (first byte lowest) -> 24-bit group a<<18|b<<12|c<<6|d.
 __device__ __forceinline__ uint32_t quad_bits(uint32_t v)
 {
     return ((v & 0x3f) << 18) | (((v >> 8) & 0x3f) << 12) | (((v >> 16) & 0x3f) << 6) | ((v >> 24) & 0x3f);
 }
 
+// Tile = BLOCK * 16 * CPL bytes, loaded as 16-byte chunks (k * BLOCK + tid)
+// and staged in LDS; classification and compaction then work on dwords
+// d = k2 * BLOCK + tid (k2 < 4 * CPL), so that lanes touch consecutive LDS
+// words and memory order is (k2, wave, lane, byte).
 template <int BLOCK, int CPL, bool ALIGNED>
 __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ src, int64_t n,
                                                   uint8_t *__restrict__ dst, int alpha,
-                                                  unsigned long long *__restrict__ ws)
+                                                  unsigned long long *__restrict__ ws, int64_t T)
 {
-    constexpr int TILE = BLOCK * 4 * CPL;  // input bytes per tile
+    constexpr int TILE = BLOCK * 16 * CPL;  // input bytes per tile
     constexpr int NW = BLOCK / 64;
-    constexpr int E = CPL * NW;            // (k, wave) segments, at most 128
+    constexpr int K2 = 4 * CPL;             // dwords per lane
+    constexpr int E = K2 * NW;              // (k2, wave) segments
     static_assert(E <= 128, "segment scan covers at most 128 entries");
     __shared__ uint32_t s_tab[64];
+    __shared__ __attribute__((aligned(16))) uint32_t s_raw[TILE / 4];  // raw, then class dwords
     __shared__ __attribute__((aligned(16))) uint8_t s_cls[16 + TILE + 16];
     __shared__ uint32_t s_seg[E];          // kept bytes per segment, then their exclusive prefix
     __shared__ uint32_t s_tot;
-    __shared__ unsigned long long s_t, s_P;
 
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
-    lds_fill(s_tab, c_ws.cls[alpha], 256);
-    if (tid == 0) s_t = atomicAdd(&ws[0], 1ull);
-    __syncthreads();
-    const int64_t t = (int64_t)s_t;
+    const int64_t t = blockIdx.x;
     const int64_t base = t * TILE;
+    {
+        uint32_t w[CPL][4];
+#pragma unroll
+        for (int k = 0; k < CPL; k++) tile_load16<ALIGNED>(src, n, base + 16 * ((int64_t)k * BLOCK + tid), w[k]);
+#pragma unroll
+        for (int k = 0; k < CPL; k++)
+            *(uint4 *)&s_raw[4 * (k * BLOCK + tid)] = make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
+    }
+    // exclusive prefix: stripped offset of the tile's first kept byte and the
+    // kept bytes before it
+    const WsSt pf = st_unpack(ws[WS_SLOT_WORDS + T + t]);
+    const int64_t P = (int64_t)pf.c;
+    const int r0 = (int)(P & 3);
+    lds_fill(s_tab, c_ws.cls[alpha], 256);
+    __syncthreads();
     const uint8_t *tab = (const uint8_t *)s_tab;
-    unsigned long long *status = ws + WS_SLOT_WORDS;
+    if (tid < r0) s_cls[16 - r0 + tid] = tab[(pf.r >> (8 * (r0 - 1 - tid))) & 0xff];
 
-    // 1. load and classify; lane tid holds dwords k * BLOCK + tid (k < CPL)
-    uint32_t cls[CPL], keep[CPL], pre[CPL];
+    // 1. classify (class dwords replace the raw ones) and count kept bytes;
+    // per-lane exclusive prefixes within the wave from one DPP scan per three
+    // dwords (10-bit fields: a wave keeps at most 256 bytes of a dword row)
+    uint32_t pre[K2], keepm[K2];
     uint32_t spec = 0;
 #pragma unroll
-    for (int k = 0; k < CPL; k++) {
-        const int64_t off = base + 4 * ((int64_t)k * BLOCK + tid);
-        uint32_t w;
-        if (off + 4 <= n) {
-            w = ALIGNED ? *(const uint32_t *)(src + off) : load4(src + off);
-        } else {
-            w = 0x20202020u;  // past the end: whitespace, removed
-            for (int j = 0; j < 4; j++)
-                if (off + j < n) w = (w & ~(0xffu << (8 * j))) | ((uint32_t)src[off + j] << (8 * j));
-        }
-        const uint32_t c = tab[w & 0xff] | ((uint32_t)tab[(w >> 8) & 0xff] << 8) |
-                           ((uint32_t)tab[(w >> 16) & 0xff] << 16) | ((uint32_t)tab[w >> 24] << 24);
-        cls[k] = c;
-        const uint32_t x = (~c & 0x40404040u) >> 6;  // bit 8j: byte j kept
-        keep[k] = (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xf;
-        spec |= c & ~(c << 1) & 0x80808080u;      // bit 7 set, bit 6 clear: invalid or '='
-    }
-
-    // 2. prefix counts of kept bytes in memory order (k, wave, lane, byte)
+    for (int k0 = 0; k0 < K2; k0 += 3) {
+        uint32_t packed = 0;
 #pragma unroll
-    for (int k = 0; k < CPL; k++) {
-        uint32_t p = 0, tot = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const unsigned long long bb = __ballot((keep[k] >> b) & 1);
-            p += __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u));
-            tot += (uint32_t)__popcll(bb);
+        for (int i = 0; i < 3; i++) {
+            const int k = k0 + i;
+            if (k < K2) {
+                const uint32_t x = s_raw[k * BLOCK + tid];
+                const uint32_t c = tab[x & 0xff] | ((uint32_t)tab[(x >> 8) & 0xff] << 8) |
+                                   ((uint32_t)tab[(x >> 16) & 0xff] << 16) | ((uint32_t)tab[x >> 24] << 24);
+                s_raw[k * BLOCK + tid] = c;
+                const uint32_t keep = kept4(x);
+                keepm[k] = keep;
+                spec |= c & ~(c << 1) & 0x80808080u;  // bit 7 set, bit 6 clear: invalid or '='
+                packed |= (uint32_t)__popc(keep) << (10 * i);
+            }
         }
-        pre[k] = p;
-        if (lane == 0) s_seg[k * NW + wid] = tot;
+        const uint32_t inc = wave_incl_sum(packed);
+        const uint32_t ex = inc - packed;
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int k = k0 + i;
+            if (k < K2) {
+                pre[k] = (ex >> (10 * i)) & 0x3ff;
+                if (lane == 0) s_seg[k * NW + wid] = (tot >> (10 * i)) & 0x3ff;
+            }
+        }
     }
     __syncthreads();
+    // 2. exclusive prefix over the (k2, wave) segments
     if (wid == 0) {
         const uint32_t a0 = 2 * lane < E ? s_seg[2 * lane] : 0u;
         const uint32_t a1 = 2 * lane + 1 < E ? s_seg[2 * lane + 1] : 0u;
@@ -202,84 +409,53 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     }
     __syncthreads();
 
-    // 3. compaction: kept class bytes to s_cls[16 + tile-stripped index]
-    uint32_t at[CPL];
+    // 3. compaction: kept class bytes to s_cls[16 + tile-stripped index];
+    // invalid bytes and '=' reported in original coordinates (rare)
+    const bool rare = __ballot(spec != 0) != 0;
 #pragma unroll
-    for (int k = 0; k < CPL; k++) {
-        at[k] = s_seg[k * NW + wid] + pre[k];
-        uint32_t pos = 16 + at[k];
+    for (int k = 0; k < K2; k++) {
+        const uint32_t c = s_raw[k * BLOCK + tid];
+        const uint32_t keep = keepm[k];  // bytes above 0x20
+        const uint32_t at = s_seg[k * NW + wid] + pre[k];
+        uint32_t pos = 16 + at;
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if ((keep[k] >> j) & 1) s_cls[pos++] = (uint8_t)(cls[k] >> (8 * j));
-    }
-    __syncthreads();
-    const uint32_t ktot = s_tot;
-
-    // 4. decoupled look-back (one lane)
-    if (tid == 0) {
-        uint32_t car = 0;
-        for (uint32_t i = ktot > 3 ? ktot - 3 : 0; i < ktot; i++) car = (car << 8) | s_cls[16 + i];
-        uint64_t P = 0;
-        uint32_t before = 0;
-        if (t == 0) {
-            __hip_atomic_store(&status[0], st_make(ST_INC, ktot, car), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&status[t], st_make(ST_AGG, ktot, car), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // every earlier tile took its index before this one and publishes
-            // its aggregate without waiting, so each wait below ends
-            for (int64_t j = t - 1;; j--) {
-                unsigned long long s;
-                while (((s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 62) == 0)
-                    __builtin_amdgcn_s_sleep(1);
-                before = car_join(st_car(s), before, P);
-                P += st_cnt(s);
-                if ((s >> 62) == 2) break;
-            }
-            __hip_atomic_store(&status[t], st_make(ST_INC, P + ktot, car_join(before, car, ktot)),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // carried bytes of the quad that straddles into this tile
-        const int r0 = (int)(P & 3);
-        for (int i = 0; i < r0; i++) s_cls[16 - r0 + i] = (uint8_t)(before >> (8 * (r0 - 1 - i)));
-        s_P = P;
-    }
-    __syncthreads();
-    const int64_t P = (int64_t)s_P;
-
-    // rare path: invalid bytes and '=' of this tile, in original coordinates
-    if (__ballot(spec != 0)) {
-#pragma unroll
-        for (int k = 0; k < CPL; k++) {
+            if ((keep >> j) & 1) s_cls[pos++] = (uint8_t)(c >> (8 * j));
+        if (rare) {
             const int64_t off = base + 4 * ((int64_t)k * BLOCK + tid);
             uint32_t rank = 0;
             for (int j = 0; j < 4; j++) {
-                const uint32_t cb = (cls[k] >> (8 * j)) & 0xff;
+                const uint32_t cb = (c >> (8 * j)) & 0xff;
                 if (cb == C_BAD) atomicMin(&ws[1], (unsigned long long)(off + j));
                 if (cb == C_PAD) {
                     atomicMin(&ws[2], (unsigned long long)(off + j));
-                    atomicMin(&ws[3], (unsigned long long)(P + at[k] + rank));
+                    atomicMin(&ws[3], (unsigned long long)(P + at + rank));
                 }
-                rank += (keep[k] >> j) & 1;
+                rank += (keep >> j) & 1;
             }
         }
     }
+    const uint32_t ktot = s_tot;
+    __syncthreads();
 
-    // 5. decode the quads that end in this tile: stripped bytes
+    // 4. decode the quads that end in this tile: stripped bytes
     // [P - r0, P + ktot) sit at s_cls[16 - r0 ...]
-    const int r0 = (int)(P & 3);
-    const int Q = (r0 + (int)ktot) >> 2;
+    // quads ending in this tile; never past the output capacity 3 * (n / 4)
+    const int64_t qcap = n / 4 - (P - r0) / 4;
+    const int Q = (int)max((int64_t)0, min((int64_t)((r0 + (int)min(ktot, (uint32_t)TILE)) >> 2), qcap));
     const int U = (Q + 3) >> 2;
     uint8_t *q0 = dst + 3 * ((P - r0) >> 2);
     for (int u = tid; u < U; u += BLOCK) {
+        // 16 bytes from s_cls + 16 - r0 + 16u: the aligned chunk at 16u + 16
+        // and, when r0 > 0, the dword before it
         uint32_t v0, v1, v2, v3;
+        const uint4 x = *(const uint4 *)(s_cls + 16 + 16 * u);
         if (r0 == 0) {
-            const uint4 x = *(const uint4 *)(s_cls + 16 + 16 * u);
             v0 = x.x; v1 = x.y; v2 = x.z; v3 = x.w;
         } else {
-            const uint32_t *d = (const uint32_t *)(s_cls + 12 + 16 * u);
-            const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+            const uint32_t d0 = *(const uint32_t *)(s_cls + 12 + 16 * u);
             const uint32_t sh = 4 - r0;
-            v0 = alignb(d1, d0, sh); v1 = alignb(d2, d1, sh); v2 = alignb(d3, d2, sh); v3 = alignb(d4, d3, sh);
+            v0 = alignb(x.x, d0, sh); v1 = alignb(x.y, x.x, sh); v2 = alignb(x.z, x.y, sh); v3 = alignb(x.w, x.z, sh);
         }
         const int nq = min(4, Q - 4 * u);
         uint8_t *q = q0 + 12 * (int64_t)u;
@@ -295,7 +471,8 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
             for (int i = 0; i < nq; i++) {
                 const uint32_t v = vs[i];
                 const uint32_t c2 = (v >> 16) & 0xff, c3 = v >> 24;
-                const uint32_t tq = quad_bits(v & ~((v & 0x80808080u) >> 2) & ~(v & 0x80808080u));
+                const uint32_t mk = v & 0x80808080u;
+                const uint32_t tq = quad_bits(v & ~(mk >> 2) & ~mk);
                 q[3 * i] = (uint8_t)(tq >> 16);
                 if (!(c2 == C_PAD && c3 == C_PAD)) q[3 * i + 1] = (uint8_t)(tq >> 8);
                 if (c3 != C_PAD) q[3 * i + 2] = (uint8_t)tq;
@@ -309,19 +486,22 @@ __global__ void k_dec_ws_final(const unsigned long long *__restrict__ ws, int64_
                                int64_t *__restrict__ d_len, int64_t *__restrict__ d_err)
 {
     if (threadIdx.x || blockIdx.x) return;
-    const unsigned long long s = ws[WS_SLOT_WORDS + T - 1];
-    const int64_t m = (int64_t)st_cnt(s);
-    const uint32_t last = st_car(s) & 0xff;
+    const WsSt all = st_join(st_unpack(ws[WS_SLOT_WORDS + T + T - 1]), st_unpack(ws[WS_SLOT_WORDS + T - 1]));
+    const int64_t m = (int64_t)all.c;
+    const uint32_t last = all.r & 0xff;
     const unsigned long long bad = ws[1], eq_o = ws[2], eq_s = ws[3];
     bool pad_ok = true;
     int64_t pads = 0;
     if (eq_s != ERR_NONE) {
         const int64_t e = (int64_t)eq_s;
-        pad_ok = (m & 3) == 0 && (e == m - 1 || (e == m - 2 && last == C_PAD));
+        pad_ok = (m & 3) == 0 && (e == m - 1 || (e == m - 2 && last == '='));
         pads = m - e;
     }
+    // With an invalid byte at i, the first '=' (if before i) is followed by a
+    // kept non-'=' byte and so misplaced: the first error is min(i, first
+    // '='). Without one, the counts are exact and the padding rule decides.
     unsigned long long err = bad;
-    if (!pad_ok && eq_o < err) err = eq_o;
+    if ((bad != ERR_NONE || !pad_ok) && eq_o < err) err = eq_o;
     if (err == ERR_NONE && (m & 3) != 0) err = (unsigned long long)n;
     if (err != ERR_NONE) {
         *d_len = -1;
@@ -336,42 +516,44 @@ __global__ void k_dec_ws_final(const unsigned long long *__restrict__ ws, int64_
 namespace {
 
 // Smallest tile of any launch shape: sizes the workspace.
-constexpr int64_t WS_MIN_TILE = 256 * 4 * 2;
+constexpr int64_t WS_MIN_TILE = 256 * 16;
 
 struct WsShape {
-    int block = 512;
-    int cpl = 8;
+    int block = 256;
+    int cpl = 4;
 };
 WsShape g_ws;
 
-int64_t ws_tiles(int64_t n, int tile) { return (n + tile - 1) / tile; }
+int64_t ws_tiles(int64_t n, int64_t tile) { return (n + tile - 1) / tile; }
+int64_t ws_words(int64_t T) { return WS_SLOT_WORDS + 2 * T + (T + WS_GROUP - 1) / WS_GROUP; }
 
 template <bool A>
 int launch_ws(int block, int cpl, int64_t T, const uint8_t *src, int64_t n, uint8_t *dst, int alpha,
               unsigned long long *ws, hipStream_t s)
 {
     const dim3 g((unsigned)T);
+    const unsigned G = (unsigned)((T + WS_GROUP - 1) / WS_GROUP);
 #define B64_WS_CASE(B, C)                                                                      \
     if (block == B && cpl == C) {                                                              \
-        hipLaunchKernelGGL((k_dec_ws<B, C, A>), g, B, 0, s, src, n, dst, alpha, ws);           \
+        hipLaunchKernelGGL((k_ws_count<B, C, A>), g, B, 0, s, src, n, ws);                     \
+        hipLaunchKernelGGL(k_ws_reduce, G, WS_SCAN_BLOCK, 0, s, ws, T);                        \
+        hipLaunchKernelGGL(k_ws_prefix, G, WS_SCAN_BLOCK, 0, s, ws, T);                        \
+        hipLaunchKernelGGL((k_dec_ws<B, C, A>), g, B, 0, s, src, n, dst, alpha, ws, T);        \
         return B64_OK;                                                                         \
     }
-    B64_WS_CASE(256, 2) B64_WS_CASE(256, 4) B64_WS_CASE(256, 8)
-    B64_WS_CASE(512, 2) B64_WS_CASE(512, 4) B64_WS_CASE(512, 8)
-    B64_WS_CASE(1024, 2) B64_WS_CASE(1024, 4) B64_WS_CASE(1024, 8)
+    B64_WS_CASE(256, 1) B64_WS_CASE(256, 2) B64_WS_CASE(256, 4) B64_WS_CASE(256, 8)
+    B64_WS_CASE(512, 1) B64_WS_CASE(512, 2) B64_WS_CASE(512, 4)
+    B64_WS_CASE(1024, 1) B64_WS_CASE(1024, 2)
 #undef B64_WS_CASE
     return b64i_fail(B64_BAD_ARG, "unsupported whitespace-decode shape %d x %d", block, cpl);
 }
 
-// Enqueues init, tile kernel and verdict. n >= 1.
+// Enqueues the count, scan, decode and verdict kernels. n >= 1.
 int enqueue_ws(const uint8_t *src, int64_t n, uint8_t *dst, int alpha, int64_t *d_len, int64_t *d_err,
                unsigned long long *ws, hipStream_t s)
 {
     const int block = g_ws.block, cpl = g_ws.cpl;
-    const int64_t T = ws_tiles(n, (int64_t)block * 4 * cpl);
-    const int ib = (int)std::min<int64_t>((T + 255) / 256 + 1, 4096);
-    hipLaunchKernelGGL(k_ws_init, ib, 256, 0, s, ws, T);
-    LAUNCH_TRY();
+    const int64_t T = ws_tiles(n, (int64_t)block * 16 * cpl);
     const bool al = (((uintptr_t)src) & 3) == 0;
     int rc = al ? launch_ws<true>(block, cpl, T, src, n, dst, alpha, ws, s)
                 : launch_ws<false>(block, cpl, T, src, n, dst, alpha, ws, s);
@@ -411,7 +593,7 @@ extern "C" {
 int64_t b64_decode_ws_workspace_bytes(int64_t n)
 {
     if (n < 0) return b64i_fail(B64_BAD_ARG, "negative length");
-    return 8 * (WS_SLOT_WORDS + std::max<int64_t>(ws_tiles(n, WS_MIN_TILE), 1));
+    return 8 * ws_words(std::max<int64_t>(ws_tiles(n, WS_MIN_TILE), 1));
 }
 
 int b64_decode_ws_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, int64_t *d_len,
@@ -484,8 +666,12 @@ int b64_set_ws_tune(const b64_tune *t)
     if (!t) return b64i_fail(B64_BAD_ARG, "null tune");
     const int block = t->block ? t->block : g_ws.block;
     const int cpl = t->units_per_lane ? t->units_per_lane : g_ws.cpl;
-    if ((block != 256 && block != 512 && block != 1024) || (cpl != 2 && cpl != 4 && cpl != 8))
-        return b64i_fail(B64_BAD_ARG, "whitespace-decode shape: block 256/512/1024, dwords per lane 2/4/8");
+    const bool ok = (block == 256 && (cpl == 1 || cpl == 2 || cpl == 4 || cpl == 8)) ||
+                    (block == 512 && (cpl == 1 || cpl == 2 || cpl == 4)) ||
+                    (block == 1024 && (cpl == 1 || cpl == 2));
+    if (!ok)
+        return b64i_fail(B64_BAD_ARG, "whitespace-decode shape: block 256 (1/2/4/8 chunks), 512 (1/2/4) "
+                                      "or 1024 (1/2) with 16-byte chunks per lane");
     g_ws.block = block;
     g_ws.cpl = cpl;
     return B64_OK;

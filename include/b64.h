@@ -318,8 +318,16 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
 /* Launch shape of the single-buffer kernels for one direction (0 encode,
  * 1 decode): block size, units per lane (1, 2, 4 or 8) and, in the `grid`
  * field, workgroups per compute unit (1..4096, or -1 for one workgroup per
- * tile, the default). Zero fields keep the current value. Process-wide;
- * meant for tuning sweeps. */
+ * tile, the default); zero in these fields keeps the current value. The
+ * `layout` field selects the character map and is always applied:
+ *   0  LDS byte tables (64 entries to encode, 256 to decode; the default);
+ *   1  register maps on v_perm_b32: the range offsets of Section 4.1
+ *      (Tables 4 and 5) to encode, Algorithm 3's nibble bitsets and roll
+ *      table (Section 4.2) to decode;
+ *   2  (encode only) an LDS table of 4096 character pairs, one lookup per
+ *      12 bits (worth it with a persistent grid, which amortises its 8 KiB
+ *      fill).
+ * Process-wide; meant for tuning sweeps. */
 int b64_set_single_tune(int dir, const b64_tune *t);
 
 /* Launch shape of the whitespace-tolerant decode (tuning): block 256, 512 or

@@ -141,3 +141,53 @@ def tune(direction, src, in_off, flags=None, in_off_host=None, reps=3, cands=Non
         cache[key] = entry
         save_cache(cache)
     return best, entry
+
+
+# --------------------------------------------------------- single buffer --
+# Candidates of the single-buffer kernels: character map (0 LDS byte tables,
+# 1 register maps on v_perm_b32, 2 LDS pair table for encoding) x launch shape
+# (block, units per lane, workgroups per CU with -1 = one per tile).
+SINGLE_SHAPES = ((512, 2, -1), (256, 4, -1), (1024, 2, -1), (256, 4, 8), (512, 2, 16), (1024, 2, 4))
+SINGLE_MAPS = {codec.DIR_ENCODE: (0, 1, 2), codec.DIR_DECODE: (0, 1)}
+
+
+def tune_single(direction, size, reps=5, use_cache=True, apply=True, seed=8):
+    """Best (block, units_per_lane, blocks_per_cu, char_map) of the
+    single-buffer kernel for inputs of `size` bytes (encode) or characters
+    (decode), timed on seeded random data with HIP events; cached per device
+    and power-of-two size class. Applies the winner unless apply=False."""
+    props = torch.cuda.get_device_properties(0)
+    key = f"single|{props.name}|{getattr(props, 'gcnArchName', '')}|dir{direction}|log2size{int(np.log2(max(size, 1)))}"
+    cache = load_cache() if use_cache else {}
+    if use_cache and key in cache:
+        best = cache[key]["tune"]
+    else:
+        dev = torch.device("cuda:0")
+        rng = np.random.default_rng(seed)
+        n = size if direction == codec.DIR_ENCODE else size // 4 * 3
+        x = torch.from_numpy(rng.integers(0, 256, max(n, 1), dtype=np.uint8)).to(dev)
+        text = codec.encode(x)
+        out = torch.empty(codec.decoded_max(text.numel()), dtype=torch.uint8, device=dev)
+        res = torch.zeros(2, dtype=torch.int64, device=dev)
+        results = []
+        for cm in SINGLE_MAPS[direction]:
+            for b, u, g in SINGLE_SHAPES:
+                codec.set_single_tune(direction, b, u, g, cm)
+                if direction == codec.DIR_ENCODE:
+                    fn = lambda: codec.encode(x, out=text)
+                else:
+                    fn = lambda: codec.decode_async(text, out, res)
+                results.append((time_call(fn, reps), {"block": b, "units_per_lane": u, "blocks_per_cu": g,
+                                                       "char_map": cm}))
+        results.sort(key=lambda r: r[0])
+        best = results[0][1]
+        if use_cache:
+            cache[key] = {"tune": best, "ms": round(results[0][0], 5), "worst_ms": round(results[-1][0], 5),
+                          "candidates": len(results)}
+            save_cache(cache)
+    if apply:
+        codec.set_single_tune(direction, best["block"], best["units_per_lane"], best["blocks_per_cu"],
+                              best["char_map"])
+    else:
+        codec.set_single_tune(direction, 512, 2, -1, 0)
+    return best

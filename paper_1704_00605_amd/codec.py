@@ -162,8 +162,11 @@ def set_ws_tune(block=0, dwords_per_lane=0):
     check(lib().b64_set_ws_tune(ctypes.byref(t)), "b64_set_ws_tune")
 
 
-def set_single_tune(direction, block=0, units_per_lane=0, blocks_per_cu=0):
-    t = Tune(block=block, units_per_lane=units_per_lane, grid=blocks_per_cu, layout=0)
+def set_single_tune(direction, block=0, units_per_lane=0, blocks_per_cu=0, char_map=0):
+    """Launch shape and character map of the single-buffer kernels (see
+    b64_set_single_tune); char_map 0 LDS tables, 1 register maps, 2 (encode)
+    pair table."""
+    t = Tune(block=block, units_per_lane=units_per_lane, grid=blocks_per_cu, layout=char_map)
     check(lib().b64_set_single_tune(int(direction), ctypes.byref(t)), "b64_set_single_tune")
 
 

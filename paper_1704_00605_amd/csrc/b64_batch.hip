@@ -475,7 +475,7 @@ __global__ __launch_bounds__(1024) void k_enc_batch_t(
         const uint8_t *p = src + msgs.b(m);
         uint8_t *q = dst + out_off[m];
         const int fl = flags ? flags[m] : 0;
-        const uint8_t *tab = tabs + 64 * (fl & M_URL);
+        const MapCtx tab{tabs + 64 * (fl & M_URL)};
         const int64_t j0 = t0 - u0, j1 = t1 - u0;
         const bool whole = t1 - t0 == (int64_t)blockDim.x * UPL;
         if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0) {
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(1024) void k_dec_batch_t(
         const uint8_t *p = src + msgs.b(m);
         uint8_t *q = dst + out_off[m];
         const int fl = flags ? flags[m] : 0;
-        const uint8_t *tab = tabs + 256 * (fl & M_URL);
+        const MapCtx tab{tabs + 256 * (fl & M_URL)};
         unsigned long long *slot = (unsigned long long *)&err_off[m];
         const int64_t j0 = t0 - u0, j1 = t1 - u0;
         const bool whole = t1 - t0 == (int64_t)blockDim.x * UPL;

@@ -196,6 +196,205 @@ __device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64
     return -1;
 }
 
+// -------------------------------------------- register and pair maps --
+// Alternatives to the LDS byte tables, chosen per launch (map 0 = LDS byte
+// tables, the default):
+//   map 1  the paper's vector translations with v_perm_b32 as a 4-byte-wide
+//          lookup over 8-entry tables: encoding adds a per-range offset
+//          (Section 4.1, Tables 4 and 5: ranges [0,26), [26,52), [52,62), 62,
+//          63); decoding validates with nibble bitsets and adds an offset
+//          looked up by the high nibble (Section 4.2, Algorithm 3).
+//   map 2  (encode) a 4096-entry table of character pairs in LDS, one lookup
+//          per 12 bits, in the spirit of the scalar table codecs the paper
+//          compares against (Section 3).
+// All constants are derived here from Table 1 and its base64url variant.
+struct PermMaps {
+    uint32_t enc_off[2][2];   // [alphabet]: offsets of range index 0..4 (bytes of a 64-bit pair)
+    uint32_t dec_lo[2][4];    // [alphabet]: bitsets by low nibble 0..15
+    uint32_t dec_hi[2][2];    // [alphabet]: class bit by high nibble 0..7 (8..15: 0x10)
+    uint32_t dec_roll[2][2];  // [alphabet]: offset by index 0..7 (index 1: the symbol of value 63)
+    uint32_t special[2];      // [alphabet]: the symbol of value 63 in all four bytes
+    int consistent;           // 1 when the tables reproduce Table 1 (checked at compile time)
+};
+
+constexpr PermMaps make_perm_maps()
+{
+    PermMaps m{};
+    const Tables t = make_tables();
+    m.consistent = 1;
+    for (int a = 0; a < 2; a++) {
+        // encode: offsets B(v) - v, constant on each range
+        const int starts[5] = {0, 26, 52, 62, 63};
+        uint8_t off[8] = {};
+        for (int r = 0; r < 5; r++) off[r] = (uint8_t)(t.enc[a][starts[r]] - starts[r]);
+        for (int v = 0; v < 64; v++) {
+            int r = (v >= 26) + (v >= 52) + (v >= 62) + (v >= 63);
+            if ((uint8_t)(v + off[r]) != t.enc[a][v]) m.consistent = 0;
+        }
+        m.enc_off[a][0] = off[0] | (off[1] << 8) | (off[2] << 16) | ((uint32_t)off[3] << 24);
+        m.enc_off[a][1] = off[4];
+        // decode: the low nibbles valid under each high nibble define classes;
+        // the empty class (high nibbles without symbols, 8..15 included) gets
+        // bit 0x10, the others bits 0x01, 0x02, 0x04, 0x08, 0x20, 0x40, 0x80
+        const uint8_t bits[7] = {0x01, 0x02, 0x04, 0x08, 0x20, 0x40, 0x80};
+        uint32_t cls_set[8] = {};
+        uint8_t cls_bit[8] = {};
+        int ncls = 0;
+        uint8_t hi[16] = {};
+        for (int h = 0; h < 16; h++) {
+            uint32_t set = 0;
+            for (int l = 0; l < 16; l++)
+                if (!(t.dec[a][(h << 4) | l] & INVALID)) set |= 1u << l;
+            if (!set) { hi[h] = 0x10; continue; }
+            int c = -1;
+            for (int i = 0; i < ncls; i++)
+                if (cls_set[i] == set) c = i;
+            if (c < 0) {
+                if (ncls >= 7) { m.consistent = 0; continue; }
+                c = ncls++;
+                cls_set[c] = set;
+                cls_bit[c] = bits[c];
+            }
+            hi[h] = cls_bit[c];
+            if (h >= 8) m.consistent = 0;  // symbols are ASCII
+        }
+        uint8_t lo[16] = {};
+        for (int l = 0; l < 16; l++) {
+            lo[l] = 0x10;
+            for (int i = 0; i < ncls; i++)
+                if (!(cls_set[i] & (1u << l))) lo[l] |= cls_bit[i];
+        }
+        for (int i = 0; i < 4; i++)
+            m.dec_lo[a][i] = lo[4 * i] | (lo[4 * i + 1] << 8) | (lo[4 * i + 2] << 16) | ((uint32_t)lo[4 * i + 3] << 24);
+        m.dec_hi[a][0] = hi[0] | (hi[1] << 8) | (hi[2] << 16) | ((uint32_t)hi[3] << 24);
+        m.dec_hi[a][1] = hi[4] | (hi[5] << 8) | (hi[6] << 16) | ((uint32_t)hi[7] << 24);
+        const uint8_t sp = t.enc[a][63];
+        m.special[a] = sp * 0x01010101u;
+        uint8_t roll[8] = {};
+        bool set_r[8] = {};
+        roll[1] = (uint8_t)(63 - sp);
+        set_r[1] = true;
+        for (int c = 0; c < 256; c++) {
+            if ((t.dec[a][c] & INVALID) || c == sp) continue;
+            const int h = c >> 4;
+            if (h == 1) m.consistent = 0;
+            const uint8_t r = (uint8_t)(t.dec[a][c] - c);
+            if (set_r[h] && roll[h] != r) m.consistent = 0;
+            roll[h] = r;
+            set_r[h] = true;
+        }
+        m.dec_roll[a][0] = roll[0] | (roll[1] << 8) | (roll[2] << 16) | ((uint32_t)roll[3] << 24);
+        m.dec_roll[a][1] = roll[4] | (roll[5] << 8) | (roll[6] << 16) | ((uint32_t)roll[7] << 24);
+    }
+    return m;
+}
+static_assert(make_perm_maps().consistent == 1, "register maps must reproduce Table 1");
+
+// 4096 character pairs per alphabet: entry i holds B(i >> 6) then B(i & 63).
+struct PairTables {
+    uint16_t pair[2][4096];
+};
+
+constexpr PairTables make_pair_tables()
+{
+    PairTables p{};
+    const Tables t = make_tables();
+    for (int a = 0; a < 2; a++)
+        for (int i = 0; i < 4096; i++) p.pair[a][i] = (uint16_t)(t.enc[a][i >> 6] | (t.enc[a][i & 63] << 8));
+    return p;
+}
+
+// Bytewise a + b (mod 256 per byte, no carry between bytes).
+__device__ __forceinline__ uint32_t byte_add(uint32_t a, uint32_t b)
+{
+    return ((a & 0x7f7f7f7fu) + (b & 0x7f7f7f7fu)) ^ ((a ^ b) & 0x80808080u);
+}
+
+// Bit 8j + 7 set exactly when byte j of w is zero.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t w)
+{
+    return ~(((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+}
+
+// Per-launch map context: the LDS byte table (every map uses it for tails
+// and error paths), the LDS pair table (map 2) and the register maps of the
+// selected alphabet (map 1).
+struct MapCtx {
+    const uint8_t *tab;
+    const uint16_t *tab12;
+    uint32_t e0, e1;
+    uint32_t l0, l1, l2, l3, h0, h1, r0, r1, sp;
+};
+
+// Map 1, encode: four 6-bit values (one per byte) -> four characters.
+__device__ __forceinline__ uint32_t enc_map_perm(uint32_t x, uint32_t e0, uint32_t e1)
+{
+    // range index: how many of 26, 52, 62, 63 the value reaches (no carries:
+    // values are below 64)
+    const uint32_t i = (((x + 0x66666666u) >> 7) & 0x01010101u) + (((x + 0x4c4c4c4cu) >> 7) & 0x01010101u) +
+                       (((x + 0x42424242u) >> 7) & 0x01010101u) + (((x + 0x41414141u) >> 7) & 0x01010101u);
+    return byte_add(x, perm(e1, e0, i));
+}
+
+// Map 1, decode: four characters -> four 6-bit values (one per byte); bad
+// collects nonzero bytes for characters outside the alphabet.
+__device__ __forceinline__ uint32_t dec_map_perm(uint32_t x, const MapCtx &m, uint32_t &bad)
+{
+    const uint32_t ln = x & 0x0f0f0f0fu;
+    const uint32_t hn = (x >> 4) & 0x0f0f0f0fu;
+    const uint32_t l7 = ln & 0x07070707u, h7 = hn & 0x07070707u;
+    const uint32_t lsel = ((ln >> 3) & 0x01010101u) * 0xffu;
+    const uint32_t lb = (perm(m.l3, m.l2, l7) & lsel) | (perm(m.l1, m.l0, l7) & ~lsel);
+    const uint32_t hb = perm(m.h1, m.h0, h7) | ((hn & 0x08080808u) << 1);
+    bad |= lb & hb;
+    const uint32_t esel = (zero_bytes(x ^ m.sp) >> 7) * 0xffu;  // bytes equal to the symbol of value 63
+    const uint32_t idx = (0x01010101u & esel) | (h7 & ~esel);
+    return byte_add(x, perm(m.r1, m.r0, idx));
+}
+
+template <int MAP>
+__device__ __forceinline__ void enc_unit_m(uint32_t w0, uint32_t w1, uint32_t w2, const MapCtx &m,
+                                           uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3)
+{
+    if (MAP == 0) {
+        enc_unit(w0, w1, w2, m.tab, o0, o1, o2, o3);
+        return;
+    }
+    const uint32_t g[4] = {perm(w0, w0, 0x0c000102u), perm(w0, w1, 0x0c070001u), perm(w1, w2, 0x0c060700u),
+                           perm(w2, w2, 0x0c010203u)};
+    uint32_t o[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t v = g[i];
+        if (MAP == 1) {
+            const uint32_t x = (v >> 18) | (((v >> 12) & 63) << 8) | (((v >> 6) & 63) << 16) | ((v & 63) << 24);
+            o[i] = enc_map_perm(x, m.e0, m.e1);
+        } else {
+            o[i] = (uint32_t)m.tab12[v >> 12] | ((uint32_t)m.tab12[v & 0xfff] << 16);
+        }
+    }
+    o0 = o[0]; o1 = o[1]; o2 = o[2]; o3 = o[3];
+}
+
+template <int MAP>
+__device__ __forceinline__ uint32_t dec_unit_m(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, const MapCtx &m,
+                                               uint32_t &o0, uint32_t &o1, uint32_t &o2)
+{
+    if (MAP == 0) return dec_unit(w0, w1, w2, w3, m.tab, o0, o1, o2);
+    uint32_t bad = 0;
+    const uint32_t w[4] = {w0, w1, w2, w3};
+    uint32_t t[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t v = dec_map_perm(w[i], m, bad);
+        t[i] = ((v & 63) << 18) | (((v >> 8) & 63) << 12) | (((v >> 16) & 63) << 6) | ((v >> 24) & 63);
+    }
+    o0 = perm(t[1], t[0], 0x06000102u);
+    o1 = perm(t[2], t[1], 0x05060001u);
+    o2 = perm(t[3], t[2], 0x04050600u);
+    return bad ? INVALID : 0u;
+}
+
 // ------------------------------------------------------------ memory ops --
 // Loads of `count` bytes from any address p read the aligned dwords that
 // contain them; every such dword holds at least one byte of [p, p + count),
@@ -278,9 +477,9 @@ struct __attribute__((aligned(4))) u32x4 { uint32_t x, y, z, w; };
 // One grid-stride step of the encode over one buffer: this lane's units are
 // first + k * stride for k < UPL. Without GUARD every unit is known to be in
 // range, so all UPL loads are issued before any is consumed.
-template <bool ALIGNED, int UPL, bool GUARD>
+template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0>
 __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
-                                         int64_t first, int stride, int64_t units, const uint8_t *tab)
+                                         int64_t first, int stride, int64_t units, const MapCtx &mc)
 {
     uint32_t w[UPL][3];
 #pragma unroll
@@ -300,7 +499,7 @@ __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_
         const int64_t u = first + (int64_t)k * stride;
         if (!GUARD || u < units) {
             uint32_t o[4];
-            enc_unit(w[k][0], w[k][1], w[k][2], tab, o[0], o[1], o[2], o[3]);
+            enc_unit_m<MAP>(w[k][0], w[k][1], w[k][2], mc, o[0], o[1], o[2], o[3]);
             if (ALIGNED) {
                 uint32_t *d = (uint32_t *)(dst + 16 * u);
                 __builtin_nontemporal_store(o[0], d + 0);
@@ -317,9 +516,9 @@ __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_
 // One grid-stride step of the decode over one buffer (see enc_step). Lanes of a
 // wave hold consecutive units, so the lowest erring lane of a ballot has the
 // wave's smallest offset; it alone performs the atomicMin.
-template <bool ALIGNED, int UPL, bool GUARD>
+template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0>
 __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
-                                         int64_t first, int stride, int64_t L, const uint8_t *tab,
+                                         int64_t first, int stride, int64_t L, const MapCtx &mc,
                                          unsigned long long *err_slot)
 {
     uint32_t w[UPL][4];
@@ -343,7 +542,7 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
         bad[k] = 0;
         if (!GUARD || u < L) {
             uint32_t o[3];
-            bad[k] = dec_unit(w[k][0], w[k][1], w[k][2], w[k][3], tab, o[0], o[1], o[2]);
+            bad[k] = dec_unit_m<MAP>(w[k][0], w[k][1], w[k][2], w[k][3], mc, o[0], o[1], o[2]);
             bad_any |= bad[k];
             if (ALIGNED) {
                 uint32_t *d = (uint32_t *)(dst + 12 * u);
@@ -363,7 +562,7 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
             const bool err = (bad[k] & INVALID) != 0;
             const unsigned long long ball = __ballot(err);
             if (ball && __lane_id() == __ffsll((long long)ball) - 1) {
-                const int64_t pos = 16 * u + dec_first_bad(w[k][0], w[k][1], w[k][2], w[k][3], tab);
+                const int64_t pos = 16 * u + dec_first_bad(w[k][0], w[k][1], w[k][2], w[k][3], mc.tab);
                 atomicMin(err_slot, (unsigned long long)pos);
             }
         }

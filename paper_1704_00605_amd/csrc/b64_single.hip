@@ -24,26 +24,53 @@
 using namespace b64dev;
 
 static __constant__ Tables c_tab = make_tables();
+static __constant__ PermMaps c_perm = make_perm_maps();
+static __constant__ PairTables c_pair = make_pair_tables();
+
+// Map context of one launch (see MapCtx): LDS tables filled by the caller.
+template <int MAP>
+__device__ __forceinline__ MapCtx map_ctx(const uint8_t *tab, const uint16_t *tab12, int url, bool decode)
+{
+    MapCtx m{};
+    m.tab = tab;
+    m.tab12 = tab12;
+    if (MAP == 1) {
+        if (!decode) {
+            m.e0 = c_perm.enc_off[url][0];
+            m.e1 = c_perm.enc_off[url][1];
+        } else {
+            m.l0 = c_perm.dec_lo[url][0]; m.l1 = c_perm.dec_lo[url][1];
+            m.l2 = c_perm.dec_lo[url][2]; m.l3 = c_perm.dec_lo[url][3];
+            m.h0 = c_perm.dec_hi[url][0]; m.h1 = c_perm.dec_hi[url][1];
+            m.r0 = c_perm.dec_roll[url][0]; m.r1 = c_perm.dec_roll[url][1];
+            m.sp = c_perm.special[url];
+        }
+    }
+    return m;
+}
 
 // Encode src[0, n): full units [0, n / 12) in a grid-stride loop over tiles
 // of blockDim * UPL units, then the final partial unit (Algorithm 1's tail)
 // by one lane.
-template <bool ALIGNED, int UPL>
+template <bool ALIGNED, int UPL, int MAP>
 __global__ __launch_bounds__(1024) void k_enc_single(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, int mode)
 {
     __shared__ uint32_t s_tab[16];
+    __shared__ uint32_t s_pair[MAP == 2 ? 2048 : 1];
     lds_fill(s_tab, c_tab.enc[mode & M_URL], 64);
+    if (MAP == 2) lds_fill(s_pair, (const uint8_t *)c_pair.pair[mode & M_URL], 8192);
     __syncthreads();
     const uint8_t *tab = (const uint8_t *)s_tab;
+    const MapCtx mc = map_ctx<MAP>(tab, (const uint16_t *)s_pair, mode & M_URL, false);
 
     const int64_t units = n / 12;
     const int64_t tile = (int64_t)blockDim.x * UPL;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < units; t0 += (int64_t)gridDim.x * tile) {
         if (t0 + tile <= units)
-            enc_step<ALIGNED, UPL, false>(src, dst, t0 + threadIdx.x, blockDim.x, units, tab);
+            enc_step<ALIGNED, UPL, false, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, units, mc);
         else
-            enc_step<ALIGNED, UPL, true>(src, dst, t0 + threadIdx.x, blockDim.x, units, tab);
+            enc_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, units, mc);
     }
     const int r = (int)(n - 12 * units);
     if (r && blockIdx.x == 0 && threadIdx.x == 0)
@@ -56,7 +83,7 @@ __global__ __launch_bounds__(1024) void k_enc_single(const uint8_t *__restrict__
 // launch; it ends holding the smallest offending index (or ERR_NONE). The
 // lane of the final unit writes the decoded length to *len_slot when that
 // unit is valid. k_dec_final turns the pair into the verdict.
-template <bool ALIGNED, int UPL>
+template <bool ALIGNED, int UPL, int MAP>
 __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, int mode,
                                                      unsigned long long *err_slot, int64_t *len_slot)
@@ -65,14 +92,15 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
     lds_fill(s_tab, c_tab.dec[mode & M_URL], 256);
     __syncthreads();
     const uint8_t *tab = (const uint8_t *)s_tab;
+    const MapCtx mc = map_ctx<MAP>(tab, nullptr, mode & M_URL, true);
 
     const int64_t L = (n - 1) / 16;
     const int64_t tile = (int64_t)blockDim.x * UPL;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < L; t0 += (int64_t)gridDim.x * tile) {
         if (t0 + tile <= L)
-            dec_step<ALIGNED, UPL, false>(src, dst, t0 + threadIdx.x, blockDim.x, L, tab, err_slot);
+            dec_step<ALIGNED, UPL, false, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, err_slot);
         else
-            dec_step<ALIGNED, UPL, true>(src, dst, t0 + threadIdx.x, blockDim.x, L, tab, err_slot);
+            dec_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, err_slot);
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         int nout;
@@ -80,6 +108,47 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
         const int idx = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode, &nout);
         if (idx >= 0) atomicMin(err_slot, (unsigned long long)(16 * L + idx));
         else *len_slot = 12 * L + nout;
+    }
+}
+
+// Decode of a short input (at most SMALL_UNITS interior units) by one
+// workgroup, verdict included, so that the whole call is one launch: the
+// first offending index is kept in an LDS slot (unsigned atomicMin) and
+// thread 0 writes (length, -1) or (-1, index) at the end.
+constexpr int64_t SMALL_UNITS = 16384;
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(1024) void k_dec_small(const uint8_t *__restrict__ src, int64_t n,
+                                                    uint8_t *__restrict__ dst, int mode,
+                                                    int64_t *__restrict__ d_len, int64_t *__restrict__ d_err)
+{
+    __shared__ uint32_t s_tab[64];
+    __shared__ unsigned long long s_err;
+    __shared__ int64_t s_len;
+    lds_fill(s_tab, c_tab.dec[mode & M_URL], 256);
+    if (threadIdx.x == 0) s_err = ERR_NONE;
+    __syncthreads();
+    const uint8_t *tab = (const uint8_t *)s_tab;
+    const MapCtx mc = map_ctx<0>(tab, nullptr, mode & M_URL, true);
+    const int64_t L = (n - 1) / 16;
+    if (threadIdx.x == 0) {
+        int nout;
+        const int idx = dec_tail(src + 16 * L, (int)(n - 16 * L), n, dst + 12 * L, tab, mode, &nout);
+        if (idx >= 0) atomicMin(&s_err, (unsigned long long)(16 * L + idx));
+        s_len = 12 * L + nout;
+    }
+    const int64_t tile = (int64_t)blockDim.x * 2;
+    for (int64_t t0 = 0; t0 < L; t0 += tile) {
+        if (t0 + tile <= L)
+            dec_step<ALIGNED, 2, false, 0>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, &s_err);
+        else
+            dec_step<ALIGNED, 2, true, 0>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, &s_err);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long e = s_err;
+        if (e == ERR_NONE) { *d_len = s_len; *d_err = -1; }
+        else { *d_len = -1; *d_err = (int64_t)e; }
     }
 }
 
@@ -120,6 +189,7 @@ struct Shape {
     std::atomic<int> block{512};
     std::atomic<int> upl{2};
     std::atomic<int> blocks_per_cu{0};
+    std::atomic<int> map{0};  // 0 LDS byte tables, 1 register maps, 2 (encode) LDS pair table
 };
 Shape g_single[2];
 
@@ -165,29 +235,38 @@ int single_grid(int dir, int64_t units, int *block, int *upl, int *grid)
     return B64_OK;
 }
 
+#define B64_UPL_SWITCH(KERN, A, M, ...)                                                          \
+    switch (upl) {                                                                               \
+    case 1: hipLaunchKernelGGL((KERN<A, 1, M>), grid, block, 0, s, __VA_ARGS__); break;          \
+    case 2: hipLaunchKernelGGL((KERN<A, 2, M>), grid, block, 0, s, __VA_ARGS__); break;          \
+    case 8: hipLaunchKernelGGL((KERN<A, 8, M>), grid, block, 0, s, __VA_ARGS__); break;          \
+    default: hipLaunchKernelGGL((KERN<A, 4, M>), grid, block, 0, s, __VA_ARGS__); break;         \
+    }
+
 template <bool A>
-void launch_enc_single(int upl, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
+void launch_enc_single(int upl, int map, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
                        int mode, hipStream_t s)
 {
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_enc_single<A, 1>), grid, block, 0, s, src, n, dst, mode); break;
-    case 2: hipLaunchKernelGGL((k_enc_single<A, 2>), grid, block, 0, s, src, n, dst, mode); break;
-    case 8: hipLaunchKernelGGL((k_enc_single<A, 8>), grid, block, 0, s, src, n, dst, mode); break;
-    default: hipLaunchKernelGGL((k_enc_single<A, 4>), grid, block, 0, s, src, n, dst, mode); break;
+    if (map == 1) {
+        B64_UPL_SWITCH(k_enc_single, A, 1, src, n, dst, mode);
+    } else if (map == 2) {
+        B64_UPL_SWITCH(k_enc_single, A, 2, src, n, dst, mode);
+    } else {
+        B64_UPL_SWITCH(k_enc_single, A, 0, src, n, dst, mode);
     }
 }
 
 template <bool A>
-void launch_dec_single(int upl, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
+void launch_dec_single(int upl, int map, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
                        int mode, unsigned long long *slot, int64_t *len_slot, hipStream_t s)
 {
-    switch (upl) {
-    case 1: hipLaunchKernelGGL((k_dec_single<A, 1>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    case 2: hipLaunchKernelGGL((k_dec_single<A, 2>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    case 8: hipLaunchKernelGGL((k_dec_single<A, 8>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
-    default: hipLaunchKernelGGL((k_dec_single<A, 4>), grid, block, 0, s, src, n, dst, mode, slot, len_slot); break;
+    if (map == 1) {
+        B64_UPL_SWITCH(k_dec_single, A, 1, src, n, dst, mode, slot, len_slot);
+    } else {
+        B64_UPL_SWITCH(k_dec_single, A, 0, src, n, dst, mode, slot, len_slot);
     }
 }
+#undef B64_UPL_SWITCH
 
 bool aligned4(const void *a, const void *b)
 {
@@ -201,8 +280,9 @@ int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, h
     int block, upl, grid;
     int rc = single_grid(0, n / 12, &block, &upl, &grid);
     if (rc) return rc;
-    if (aligned4(src, dst)) launch_enc_single<true>(upl, grid, block, src, n, dst, mode, s);
-    else launch_enc_single<false>(upl, grid, block, src, n, dst, mode, s);
+    const int map = g_single[0].map.load();
+    if (aligned4(src, dst)) launch_enc_single<true>(upl, map, grid, block, src, n, dst, mode, s);
+    else launch_enc_single<false>(upl, map, grid, block, src, n, dst, mode, s);
     LAUNCH_TRY();
     return B64_OK;
 }
@@ -215,8 +295,22 @@ int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, u
     int block, upl, grid;
     int rc = single_grid(1, (n - 1) / 16, &block, &upl, &grid);
     if (rc) return rc;
-    if (aligned4(src, dst)) launch_dec_single<true>(upl, grid, block, src, n, dst, mode, slot, len_slot, s);
-    else launch_dec_single<false>(upl, grid, block, src, n, dst, mode, slot, len_slot, s);
+    const int map = g_single[1].map.load();
+    if (aligned4(src, dst)) launch_dec_single<true>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, s);
+    else launch_dec_single<false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, s);
+    LAUNCH_TRY();
+    return B64_OK;
+}
+
+// One-launch decode of a short input (n >= 1, at most SMALL_UNITS interior
+// units) with its verdict written to d_len / d_err.
+int b64i_enqueue_decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
+                              int64_t *d_err, hipStream_t s)
+{
+    if (aligned4(src, dst))
+        hipLaunchKernelGGL(k_dec_small<true>, 1, 1024, 0, s, src, n, dst, mode, d_len, d_err);
+    else
+        hipLaunchKernelGGL(k_dec_small<false>, 1, 1024, 0, s, src, n, dst, mode, d_len, d_err);
     LAUNCH_TRY();
     return B64_OK;
 }
@@ -254,16 +348,22 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
     if (n < 0) return b64i_fail(B64_BAD_ARG, "negative length");
     *err_off = -1;
     if (n == 0) return 0;
-    if (!src || (!dst && n >= 4)) return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
+    if (!src || (!dst && b64_decoded_max_mode(n, alphabet & ~0xff) > 0))
+        return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
     SyncSlot *sl;
     rc = sync_slot(&sl);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    rc = b64i_enqueue_decode(src, n, dst, mode, sl->d, (int64_t *)(sl->d + 1), s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, sl->d, (const int64_t *)(sl->d + 1), (int64_t *)(sl->d + 2),
-                       (int64_t *)(sl->d + 3), 1);
-    LAUNCH_TRY();
+    if ((n - 1) / 16 <= SMALL_UNITS) {
+        rc = b64i_enqueue_decode_small(src, n, dst, mode, (int64_t *)(sl->d + 2), (int64_t *)(sl->d + 3), s);
+        if (rc) return rc;
+    } else {
+        rc = b64i_enqueue_decode(src, n, dst, mode, sl->d, (int64_t *)(sl->d + 1), s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, sl->d, (const int64_t *)(sl->d + 1), (int64_t *)(sl->d + 2),
+                           (int64_t *)(sl->d + 3), 1);
+        LAUNCH_TRY();
+    }
     HIP_TRY(hipMemcpyAsync(sl->h, sl->d + 2, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const int64_t len = sl->h[0], err = sl->h[1];
@@ -287,8 +387,13 @@ int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, 
     if (rc) return rc;
     if (n < 0) return b64i_fail(B64_BAD_ARG, "negative length");
     if (!d_len || !d_err) return b64i_fail(B64_BAD_ARG, "null result slot");
-    if (n > 0 && (!src || (!dst && n >= 4))) return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
+    if (n > 0 && (!src || (!dst && b64_decoded_max_mode(n, alphabet & ~0xff) > 0)))
+        return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
     hipStream_t s = (hipStream_t)stream;
+    if (n > 0 && (n - 1) / 16 <= SMALL_UNITS) {
+        rc = b64i_enqueue_decode_small(src, n, dst, mode, d_len, d_err, s);
+        return rc;
+    }
     hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, n == 0 ? 1 : 0);
     LAUNCH_TRY();
     if (n == 0) return B64_OK;
@@ -318,6 +423,9 @@ int b64_set_single_tune(int dir, const b64_tune *t)
         if (t->grid < -1 || t->grid > 4096) return b64i_fail(B64_BAD_ARG, "blocks per CU must be -1 or 1..4096");
         g_single[dir].blocks_per_cu = t->grid < 0 ? 0 : t->grid;
     }
+    if (t->layout < 0 || t->layout > (dir == 0 ? 2 : 1))
+        return b64i_fail(B64_BAD_ARG, "map must be 0 (LDS tables), 1 (register maps) or, for encode, 2 (pair table)");
+    g_single[dir].map = t->layout;
     return B64_OK;
 }
 

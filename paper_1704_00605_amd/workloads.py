@@ -201,3 +201,24 @@ def mime_1gib(seed=5):
     rng = np.random.default_rng(seed)
     return {"payload": random_bytes(rng, 1 << 30), "width": 76, "eol": b"\r\n",
             "corrupt_u": float(rng.uniform()), "corrupt_rank": int(rng.integers(0, 192))}
+
+
+# ---------------------------------------------------------- file sizes --
+# Base64 text sizes of the six files of the paper's decoding table (Section
+# 5, Table 7: three JPEG images, a text quote, two PNG images). The files are
+# not available; uniform random payloads stand in for them. A padded text has
+# a length divisible by 4, so 2,357 and 1,355 round down to 2,356 and 1,352.
+TABLE7_SIZES = (("lena [jpg]", 141_020), ("peppers [jpg]", 12_640), ("mandril [jpg]", 329_632),
+                ("Moby Dick [text]", 1_484), ("google logo [png]", 2_357), ("bing social icons [png]", 1_355))
+
+
+def table7_files(seed=6):
+    """[(name, stated size, payload)]: a payload of 3 * L / 4 - 1 random
+    bytes encodes to a text of exactly L = 4 * floor(size / 4) characters
+    ending in one '='."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, size in TABLE7_SIZES:
+        L = size // 4 * 4
+        out.append((name, size, random_bytes(rng, 3 * L // 4 - 1)))
+    return out

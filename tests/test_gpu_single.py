@@ -242,3 +242,16 @@ def test_config2_one_gib_sampled():
     assert ow[:2] == (-1, pos - lo)
     out, err = codec.decode(t)
     assert out is None and err == pos
+
+
+def test_table7_file_sizes_match_oracle():
+    """Texts at the six sizes of the paper's decoding table (synthetic
+    payloads): encode and decode agree with the oracle byte for byte."""
+    from paper_1704_00605_amd import workloads
+    for name, size, payload in workloads.table7_files():
+        t = codec.encode(torch.from_numpy(payload).to("cuda:0"))
+        want = oracle.encode(payload)
+        assert t.numel() == size // 4 * 4 and np.array_equal(t.cpu().numpy(), want), name
+        out, err = codec.decode(t)
+        w = oracle.decode(want)
+        assert err == -1 and out.numel() == w[0] and np.array_equal(out.cpu().numpy(), w[2]), name

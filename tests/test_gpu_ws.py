@@ -47,7 +47,7 @@ def check(a, alphabet=0, shift=0):
 @pytest.fixture(autouse=True)
 def default_shape():
     yield
-    codec.set_ws_tune(256, 4)
+    codec.set_ws_tune(256, 2)
 
 
 def test_ws_small_random_cases():

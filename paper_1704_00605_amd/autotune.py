@@ -4,7 +4,7 @@ Searches the work layout (grid-stride tiles, or one contiguous range of
 64-unit groups per wave) and the launch shape (threads per workgroup, units
 per lane, workgroups in the persistent grid) of ``b64_encode_batch`` /
 ``b64_decode_batch`` on the actual batch, timing each candidate with HIP events, and caches the winner in
-a JSON file keyed by device, architecture, direction and a coarse signature
+a JSON file keyed by architecture, compute-unit count, direction and a coarse signature
 of the batch (message count, total bytes and the log2 histogram of message
 lengths). The tile of one workgroup step is ``block * units_per_lane``
 units of 12 bytes (encode) or 16 characters (decode); how many messages share
@@ -50,10 +50,15 @@ def signature(in_off_host):
             "hist": [float(x) for x in frac]}
 
 
-def _key(direction, sig):
+def _device_key():
+    # architecture and compute-unit count (the marketing name can differ
+    # between processes, e.g. under a profiler)
     props = torch.cuda.get_device_properties(0)
-    arch = getattr(props, "gcnArchName", "unknown")
-    return f"{props.name}|{arch}|dir{direction}|{json.dumps(sig, sort_keys=True)}"
+    return f"{getattr(props, 'gcnArchName', 'unknown')}|cus{props.multi_processor_count}"
+
+
+def _key(direction, sig):
+    return f"{_device_key()}|dir{direction}|{json.dumps(sig, sort_keys=True)}"
 
 
 def load_cache():
@@ -156,8 +161,7 @@ def tune_single(direction, size, reps=5, use_cache=True, apply=True, seed=8):
     single-buffer kernel for inputs of `size` bytes (encode) or characters
     (decode), timed on seeded random data with HIP events; cached per device
     and power-of-two size class. Applies the winner unless apply=False."""
-    props = torch.cuda.get_device_properties(0)
-    key = f"single|{props.name}|{getattr(props, 'gcnArchName', '')}|dir{direction}|log2size{int(np.log2(max(size, 1)))}"
+    key = f"single|{_device_key()}|dir{direction}|log2size{int(np.log2(max(size, 1)))}"
     cache = load_cache() if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]["tune"]
@@ -189,5 +193,5 @@ def tune_single(direction, size, reps=5, use_cache=True, apply=True, seed=8):
         codec.set_single_tune(direction, best["block"], best["units_per_lane"], best["blocks_per_cu"],
                               best["char_map"])
     else:
-        codec.set_single_tune(direction, 512, 2, -1, 0)
+        codec.set_single_tune(direction, 512 if direction == codec.DIR_ENCODE else 256, 2, -1, 0)
     return best

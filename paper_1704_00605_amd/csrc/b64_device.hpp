@@ -486,9 +486,11 @@ __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_
     for (int k = 0; k < UPL; k++) {
         const int64_t u = first + (int64_t)k * stride;
         if (!GUARD || u < units) {
-            if (ALIGNED) {
-                const u32x3 v = *(const u32x3 *)(src + 12 * u);
-                w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z;
+            if (ALIGNED) {  // streamed: read once, so non-temporal
+                const uint32_t *p = (const uint32_t *)(src + 12 * u);
+                w[k][0] = __builtin_nontemporal_load(p);
+                w[k][1] = __builtin_nontemporal_load(p + 1);
+                w[k][2] = __builtin_nontemporal_load(p + 2);
             } else {
                 load12(src + 12 * u, w[k][0], w[k][1], w[k][2]);
             }
@@ -526,9 +528,12 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
     for (int k = 0; k < UPL; k++) {
         const int64_t u = first + (int64_t)k * stride;
         if (!GUARD || u < L) {
-            if (ALIGNED) {
-                const u32x4 v = *(const u32x4 *)(src + 16 * u);
-                w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z; w[k][3] = v.w;
+            if (ALIGNED) {  // streamed: read once, so non-temporal
+                const uint32_t *p = (const uint32_t *)(src + 16 * u);
+                w[k][0] = __builtin_nontemporal_load(p);
+                w[k][1] = __builtin_nontemporal_load(p + 1);
+                w[k][2] = __builtin_nontemporal_load(p + 2);
+                w[k][3] = __builtin_nontemporal_load(p + 3);
             } else {
                 load16(src + 16 * u, w[k][0], w[k][1], w[k][2], w[k][3]);
             }

@@ -181,17 +181,18 @@ __global__ void k_slots_init(int64_t *d_len, int64_t *d_err, int empty)
 namespace {
 
 // Launch shapes of the single-buffer kernels (settable for tuning sweeps).
-// Default: 512 lanes x 2 units per workgroup and one workgroup per tile
-// (blocks_per_cu == 0), the fastest shape of a sweep over block {256, 512,
-// 1024} x units {1, 2, 4, 8} x grid {2..64 per CU, one-shot} on MI355X for
-// both directions at 1 GiB.
+// Defaults: one workgroup per tile (blocks_per_cu == 0) with 2 units per
+// lane, 512 lanes to encode and 256 to decode: the fastest shapes of a sweep
+// over block {256, 512, 1024} x units {1, 2, 4} x grid {8, 16, 32 per CU,
+// one-shot} on MI355X at 1 GiB.
 struct Shape {
-    std::atomic<int> block{512};
+    Shape(int b) : block(b) {}
+    std::atomic<int> block;
     std::atomic<int> upl{2};
     std::atomic<int> blocks_per_cu{0};
     std::atomic<int> map{0};  // 0 LDS byte tables, 1 register maps, 2 (encode) LDS pair table
 };
-Shape g_single[2];
+Shape g_single[2] = {512, 256};
 
 // Per-thread, per-device result slots of the synchronous decode:
 // [0] error slot (u64, kept at ERR_NONE between calls), [1] length written by

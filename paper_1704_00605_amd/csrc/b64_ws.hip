@@ -140,8 +140,11 @@ __device__ __forceinline__ void tile_load16(const uint8_t *__restrict__ src, int
 {
     if (off + 16 <= n) {
         if (ALIGNED) {
-            const uint4 v = *(const uint4 *)(src + off);
-            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            const uint32_t *p = (const uint32_t *)(src + off);
+            w[0] = __builtin_nontemporal_load(p);
+            w[1] = __builtin_nontemporal_load(p + 1);
+            w[2] = __builtin_nontemporal_load(p + 2);
+            w[3] = __builtin_nontemporal_load(p + 3);
         } else {
             load16(src + off, w[0], w[1], w[2], w[3]);
         }

@@ -19,7 +19,7 @@ DEC_MAPS = [0, 1]
 def restore_defaults():
     yield
     codec.set_single_tune(0, 512, 2, -1, 0)
-    codec.set_single_tune(1, 512, 2, -1, 0)
+    codec.set_single_tune(1, 256, 2, -1, 0)
 
 
 def dev(a):

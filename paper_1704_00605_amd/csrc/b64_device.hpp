@@ -85,6 +85,57 @@ __device__ __forceinline__ void enc_unit(uint32_t w0, uint32_t w1, uint32_t w2, 
     o3 = enc_quad(perm(w2, w2, 0x0c010203u), tab);
 }
 
+// ----------------------------------------------------- register tails --
+// Byte i (0..15) of four little-endian words, by a select chain (no
+// dynamic register indexing, so no scratch memory).
+__device__ __forceinline__ uint32_t byte_of(const uint32_t (&w)[4], int i)
+{
+    const uint32_t x = i < 4 ? w[0] : i < 8 ? w[1] : i < 12 ? w[2] : w[3];
+    return (x >> (8 * (i & 3))) & 0xffu;
+}
+
+// r bytes (1..16) at p into w (zero beyond r). Only the aligned dwords that
+// hold a byte of [p, p + r) are read, all in one round of predicated loads.
+__device__ __forceinline__ void load_upto16(const uint8_t *p, int r, uint32_t (&w)[4])
+{
+    const uint32_t s = (uint32_t)((uintptr_t)p & 3);
+    const uint32_t *d = (const uint32_t *)(p - s);
+    const int nd = ((int)s + r + 3) >> 2;  // 1..5
+    uint32_t x[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) x[k] = k < nd ? d[k] : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        uint32_t v = s ? alignb(x[k + 1], x[k], s) : x[k];
+        const int keep = r - 4 * k;  // bytes of this word inside the run
+        v = keep >= 4 ? v : keep <= 0 ? 0u : (v & ((1u << (8 * keep)) - 1u));
+        w[k] = v;
+    }
+}
+
+// Writes c bytes (0..16) held little-endian in o to q: whole dwords when q is
+// 4-byte aligned, then the partial dword; byte stores otherwise.
+__device__ __forceinline__ void store_upto16(uint8_t *q, const uint32_t (&o)[4], int c)
+{
+    if ((((uintptr_t)q) & 3) == 0) {
+        uint32_t *d = (uint32_t *)q;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (4 * k + 4 <= c) d[k] = o[k];
+        const int full = c >> 2, rest = c & 3;
+        if (rest) {
+            const uint32_t v = full == 0 ? o[0] : full == 1 ? o[1] : full == 2 ? o[2] : o[3];
+            uint8_t *e = q + 4 * full;
+            if (rest & 2) { *(uint16_t *)e = (uint16_t)v; e += 2; }
+            if (rest & 1) *e = (uint8_t)(rest & 2 ? v >> 16 : v);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (i < c) q[i] = (uint8_t)byte_of(o, i);
+    }
+}
+
 // Final partial unit of a message: r bytes (1..12) at s. Writes the
 // characters of Algorithm 1 (including its tail: one leftover byte -> two
 // characters, two -> three, then '=' padding unless nopad) to q and returns
@@ -92,21 +143,30 @@ __device__ __forceinline__ void enc_unit(uint32_t w0, uint32_t w1, uint32_t w2, 
 __device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
                                      const uint8_t *tab, int nopad)
 {
-    int o = 0;
-    for (int i = 0; i < r; i += 3) {
-        uint32_t b0 = s[i];
-        uint32_t b1 = (i + 1 < r) ? s[i + 1] : 0u;
-        uint32_t b2 = (i + 2 < r) ? s[i + 2] : 0u;
-        uint32_t v = (b0 << 16) | (b1 << 8) | b2;
-        int left = r - i;  // 1, 2 or >= 3
-        q[o++] = tab[v >> 18];
-        q[o++] = tab[(v >> 12) & 63];
-        if (left >= 2) q[o++] = tab[(v >> 6) & 63];
-        else if (!nopad) q[o++] = '=';
-        if (left >= 3) q[o++] = tab[v & 63];
-        else if (!nopad) q[o++] = '=';
+    uint32_t w[4];
+    load_upto16(s, r, w);
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int left = r - 3 * i;  // bytes from this group on
+        if (left <= 0) break;
+        const uint32_t v = (byte_of(w, 3 * i) << 16) | (byte_of(w, 3 * i + 1) << 8) | byte_of(w, 3 * i + 2);
+        uint32_t ch[4] = {tab[v >> 18], tab[(v >> 12) & 63], left >= 2 ? tab[(v >> 6) & 63] : (uint32_t)'=',
+                          left >= 3 ? tab[v & 63] : (uint32_t)'='};
+        const int emit = nopad ? (left >= 3 ? 4 : left + 1) : 4;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (j < emit) {
+                const int at = c + j;  // at < 16
+                const uint32_t sh = 8 * (at & 3), bits = ch[j] << sh;
+                if (at < 4) o[0] |= bits; else if (at < 8) o[1] |= bits; else if (at < 12) o[2] |= bits; else o[3] |= bits;
+            }
+        }
+        c += emit;
     }
-    return o;
+    store_upto16(q, o, c);
+    return c;
 }
 
 // ------------------------------------------------------ decode (a7,a9) --
@@ -156,43 +216,59 @@ __device__ __noinline__ int dec_first_bad(uint32_t w0, uint32_t w1, uint32_t w2,
 // check (Appendix A), and writes the decoded bytes to q. Returns the first
 // offending index relative to c (r stands for "length error at n"), or -1;
 // *nout receives the number of bytes written (0 when an error was found).
+// The characters are loaded once into registers.
 __device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64_t n,
                                      uint8_t *__restrict__ q, const uint8_t *tab, int mode,
                                      int *nout)
 {
+    uint32_t w[4];
+    load_upto16(c, r, w);
     const bool nopad = (mode & M_NOPAD) != 0;
     int pads = 0;
-    if (!nopad && (n & 3) == 0 && r >= 1 && c[r - 1] == '=') {
+    if (!nopad && (n & 3) == 0 && byte_of(w, r - 1) == '=') {
         pads = 1;
-        if (r >= 2 && c[r - 2] == '=') pads = 2;
+        if (r >= 2 && byte_of(w, r - 2) == '=') pads = 2;
     }
     *nout = 0;
-    for (int k = 0; k < r - pads; k++)
-        if (tab[c[k]] & INVALID) return k;
+    uint32_t val[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        val[k] = 0;
+        if (k < r - pads) {
+            const uint32_t v = tab[byte_of(w, k)];
+            if (v & INVALID) return k;
+            val[k] = v;
+        }
+    }
     if (nopad ? ((n & 3) == 1) : ((n & 3) != 0)) return r;
     // Appendix A (strict): leftover bits of a padded final quad must be zero.
-    if ((mode & M_STRICT) && pads == 2 && ((tab[c[r - 3]] * 16) & 255) != 0) return r - 3;
-    if ((mode & M_STRICT) && pads == 1 && ((tab[c[r - 2]] * 64) & 255) != 0) return r - 2;
-    int o = 0;
-    const int full = r & ~3;  // characters in complete groups of 4
-    for (int k = 0; k < full; k += 4) {
-        uint32_t a = c[k] == '=' ? 0u : tab[c[k]];
-        uint32_t b = c[k + 1] == '=' ? 0u : tab[c[k + 1]];
-        uint32_t cc = c[k + 2] == '=' ? 0u : tab[c[k + 2]];
-        uint32_t d = c[k + 3] == '=' ? 0u : tab[c[k + 3]];
-        uint32_t t = (a << 18) | (b << 12) | (cc << 6) | d;
-        q[o++] = (uint8_t)(t >> 16);
-        if (c[k + 2] != '=') q[o++] = (uint8_t)(t >> 8);
-        if (c[k + 3] != '=') q[o++] = (uint8_t)t;
+    if ((mode & M_STRICT) && pads == 2 && ((tab[byte_of(w, r - 3)] * 16) & 255) != 0) return r - 3;
+    if ((mode & M_STRICT) && pads == 1 && ((tab[byte_of(w, r - 2)] * 64) & 255) != 0) return r - 2;
+    // groups of four (pads read as 0), then an unpadded trailing group of 2 or 3
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+    int cnt = 0;
+    const int full = r & ~3;
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        const int k = 4 * g;
+        int nb = 0;
+        if (k + 4 <= full) nb = 3 - (k + 4 == r ? pads : 0);
+        else if (nopad && k == full && (r & 3) >= 2) nb = (r & 3) - 1;
+        if (nb == 0) continue;
+        const uint32_t t = (val[k] << 18) | (val[k + 1] << 12) | (val[k + 2] << 6) | val[k + 3];
+        const uint32_t b3[3] = {(t >> 16) & 255, (t >> 8) & 255, t & 255};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            if (j < nb) {
+                const int at = cnt + j;  // at < 12
+                const uint32_t bits = b3[j] << (8 * (at & 3));
+                if (at < 4) o[0] |= bits; else if (at < 8) o[1] |= bits; else o[2] |= bits;
+            }
+        }
+        cnt += nb;
     }
-    if (nopad && (r & 3) >= 2) {  // trailing group of 2 or 3 characters
-        uint32_t a = tab[c[full]], b = tab[c[full + 1]];
-        uint32_t cc = (r & 3) == 3 ? tab[c[full + 2]] : 0u;
-        uint32_t t = (a << 18) | (b << 12) | (cc << 6);
-        q[o++] = (uint8_t)(t >> 16);
-        if ((r & 3) == 3) q[o++] = (uint8_t)(t >> 8);
-    }
-    *nout = o;
+    store_upto16(q, o, cnt);
+    *nout = cnt;
     return -1;
 }
 
@@ -396,34 +472,39 @@ __device__ __forceinline__ uint32_t dec_unit_m(uint32_t w0, uint32_t w1, uint32_
 }
 
 // ------------------------------------------------------------ memory ops --
+struct __attribute__((aligned(4))) u32x3 { uint32_t x, y, z; };
+struct __attribute__((aligned(4))) u32x4 { uint32_t x, y, z, w; };
+
 // Loads of `count` bytes from any address p read the aligned dwords that
-// contain them; every such dword holds at least one byte of [p, p + count),
-// so it lies on a page that the buffer occupies.
+// contain them: at offset s = p mod 4 > 0, one 4-byte-aligned 16-byte load
+// at p - s (plus a dword for 16 bytes), whose last dword still holds a byte
+// of [p, p + count), so every dword read lies on a page the buffer occupies.
+// Pointer arithmetic (not integer casts) keeps the global address space, so
+// these compile to global (not flat) loads.
 __device__ __forceinline__ void load12(const uint8_t *p, uint32_t &w0, uint32_t &w1, uint32_t &w2)
 {
-    const uintptr_t a = (uintptr_t)p;
-    const uint32_t *d = (const uint32_t *)(a & ~(uintptr_t)3);
-    const uint32_t s = (uint32_t)(a & 3);
+    const uint32_t s = (uint32_t)((uintptr_t)p & 3);
     if (s == 0) {
-        w0 = d[0]; w1 = d[1]; w2 = d[2];
+        const u32x3 v = *(const u32x3 *)p;
+        w0 = v.x; w1 = v.y; w2 = v.z;
     } else {
-        uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
-        w0 = alignb(d1, d0, s); w1 = alignb(d2, d1, s); w2 = alignb(d3, d2, s);
+        const u32x4 v = *(const u32x4 *)(p - s);
+        w0 = alignb(v.y, v.x, s); w1 = alignb(v.z, v.y, s); w2 = alignb(v.w, v.z, s);
     }
 }
 
 __device__ __forceinline__ void load16(const uint8_t *p, uint32_t &w0, uint32_t &w1, uint32_t &w2,
                                        uint32_t &w3)
 {
-    const uintptr_t a = (uintptr_t)p;
-    const uint32_t *d = (const uint32_t *)(a & ~(uintptr_t)3);
-    const uint32_t s = (uint32_t)(a & 3);
+    const uint32_t s = (uint32_t)((uintptr_t)p & 3);
     if (s == 0) {
-        w0 = d[0]; w1 = d[1]; w2 = d[2]; w3 = d[3];
+        const u32x4 v = *(const u32x4 *)p;
+        w0 = v.x; w1 = v.y; w2 = v.z; w3 = v.w;
     } else {
-        uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
-        w0 = alignb(d1, d0, s); w1 = alignb(d2, d1, s); w2 = alignb(d3, d2, s);
-        w3 = alignb(d4, d3, s);
+        const u32x4 v = *(const u32x4 *)(p - s);
+        const uint32_t d4 = *(const uint32_t *)(p - s + 16);
+        w0 = alignb(v.y, v.x, s); w1 = alignb(v.z, v.y, s); w2 = alignb(v.w, v.z, s);
+        w3 = alignb(d4, v.w, s);
     }
 }
 
@@ -439,8 +520,7 @@ __device__ __forceinline__ void store_edge_lo(uint8_t *q, uint32_t v, uint32_t n
 template <int K, bool NT = false>
 __device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
 {
-    const uintptr_t a = (uintptr_t)q;
-    const uint32_t s = (uint32_t)(a & 3);
+    const uint32_t s = (uint32_t)((uintptr_t)q & 3);
     if (s == 0) {
         uint32_t *d = (uint32_t *)q;
 #pragma unroll
@@ -451,7 +531,7 @@ __device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
         return;
     }
     // bytes land at offset s of the aligned window d[0 .. K]
-    uint32_t *d = (uint32_t *)(a & ~(uintptr_t)3);
+    uint32_t *d = (uint32_t *)(q - s);
     const uint32_t sh = 4 - s;  // realign: window dword j = (o[j] : o[j-1]) >> 8*sh
     // head: high (4 - s) bytes of d[0] get the first (4 - s) bytes of o[0]
     if (s == 1) { q[0] = (uint8_t)o[0]; *(uint16_t *)(q + 1) = (uint16_t)(o[0] >> 8); }
@@ -470,9 +550,6 @@ __device__ __forceinline__ void lds_fill(uint32_t *dst, const uint8_t *src, int 
     const uint32_t *s = (const uint32_t *)src;
     for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) dst[i] = s[i];
 }
-
-struct __attribute__((aligned(4))) u32x3 { uint32_t x, y, z; };
-struct __attribute__((aligned(4))) u32x4 { uint32_t x, y, z, w; };
 
 // One grid-stride step of the encode over one buffer: this lane's units are
 // first + k * stride for k < UPL. Without GUARD every unit is known to be in

@@ -125,14 +125,6 @@ constexpr int WS_SCAN_BLOCK = 256;
 constexpr int WS_SCAN_PER = 8;
 constexpr int WS_GROUP = WS_SCAN_BLOCK * WS_SCAN_PER;  // tiles per scan group
 
-__device__ __forceinline__ uint32_t load4(const uint8_t *p)
-{
-    const uintptr_t a = (uintptr_t)p;
-    const uint32_t *d = (const uint32_t *)(a & ~(uintptr_t)3);
-    const uint32_t s = (uint32_t)(a & 3);
-    return s ? alignb(d[1], d[0], s) : d[0];
-}
-
 // 16 bytes at src + off (off a multiple of 16 from the tile base); bytes
 // past the end read as spaces (removed).
 template <bool ALIGNED>

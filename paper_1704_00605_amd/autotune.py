@@ -23,7 +23,8 @@ from . import codec
 # per layout: (blocks, units per lane, workgroups per compute unit)
 SPACE = {
     0: ((256, 512, 1024), (1, 2, 4), (8, 16, 32)),
-    1: ((128, 256, 512), (1, 2, 4), (4, 8, 16)),
+    # finer per-wave shares balance the uneven per-message costs better
+    1: ((64, 128, 256), (1, 2), (16, 32, 64, 128)),
 }
 DEFAULT = {"block": 512, "units_per_lane": 2, "grid_per_cu": 32, "layout": 0}
 

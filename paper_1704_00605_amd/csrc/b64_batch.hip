@@ -9,7 +9,7 @@
 //   k_enc_batch_w / k_dec_batch_w persistent codec, wave layout: one
 //                                 contiguous range of 64-unit groups per wave.
 //   k_dec_batch_final             per-message verdicts.
-//   k_out_offsets                 exclusive scan of output sizes.
+//   k_out_reduce / k_out_scan     exclusive scan of output sizes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -546,29 +546,52 @@ __global__ void k_dec_batch_final(int64_t N, int64_t *__restrict__ out_len, int6
     }
 }
 
-// Exclusive scan of per-message output sizes by one workgroup.
-__global__ __launch_bounds__(1024) void k_out_offsets(int dir, Msgs msgs, int64_t N,
-                                                      const uint8_t *__restrict__ flags,
-                                                      int64_t *__restrict__ out_off)
+// Output size of message i for b64_batch_out_offsets: encoded length, or the
+// decode slot (capacity rounded up to a multiple of 4).
+__device__ __forceinline__ int64_t out_size_of(int dir, Msgs msgs, const uint8_t *flags, int64_t i)
 {
-    const int64_t per = (N + blockDim.x - 1) / blockDim.x;
-    const int64_t i0 = threadIdx.x * per;
-    const int64_t i1 = min(N, i0 + per);
+    const int64_t len = msgs.n(i);
+    const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
+    return dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
+}
+
+// Per-chunk totals of output sizes (chunks of PLAN_CHUNK messages).
+__global__ __launch_bounds__(PLAN_BLOCK) void k_out_reduce(int dir, Msgs msgs, int64_t N,
+                                                          const uint8_t *__restrict__ flags,
+                                                          int64_t *__restrict__ partial)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * PLAN_CHUNK + threadIdx.x * PLAN_PER_THREAD;
     int64_t s = 0;
-    for (int64_t i = i0; i < i1; i++) {
-        const int64_t len = msgs.n(i);
-        const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
-        s += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
+    for (int k = 0; k < PLAN_PER_THREAD; k++)
+        if (i0 + k < N) s += out_size_of(dir, msgs, flags, i0 + k);
+    s = block_sum(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out_off = exclusive scan of output sizes (N + 1 entries).
+__global__ __launch_bounds__(PLAN_BLOCK) void k_out_scan(int dir, Msgs msgs, int64_t N,
+                                                        const uint8_t *__restrict__ flags,
+                                                        const int64_t *__restrict__ partial,
+                                                        int64_t *__restrict__ out_off)
+{
+    int64_t pre = 0;
+    for (int64_t c = threadIdx.x; c < blockIdx.x; c += blockDim.x) pre += partial[c];
+    pre = block_sum(pre);
+    const int64_t i0 = (int64_t)blockIdx.x * PLAN_CHUNK + threadIdx.x * PLAN_PER_THREAD;
+    int64_t v[PLAN_PER_THREAD];
+    int64_t s = 0;
+    for (int k = 0; k < PLAN_PER_THREAD; k++) {
+        v[k] = i0 + k < N ? out_size_of(dir, msgs, flags, i0 + k) : 0;
+        s += v[k];
     }
-    int64_t acc = block_exclusive_scan(s);
-    for (int64_t i = i0; i < i1; i++) {
-        out_off[i] = acc;
-        const int64_t len = msgs.n(i);
-        const int nopad = flags ? (flags[i] & M_NOPAD) : 0;
-        acc += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
+    int64_t ex = pre + block_exclusive_scan(s);
+    for (int k = 0; k < PLAN_PER_THREAD; k++) {
+        const int64_t i = i0 + k;
+        if (i < N) out_off[i] = ex;
+        if (i == N - 1) out_off[N] = ex + v[k];
+        ex += v[k];
     }
-    if (i0 < N && i1 == N) out_off[N] = acc;
-    if (N == 0 && threadIdx.x == 0) out_off[0] = 0;
+    if (N == 0 && blockIdx.x == 0 && threadIdx.x == 0) out_off[0] = 0;
 }
 
 // ================================================================= host ==
@@ -586,9 +609,22 @@ int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *ou
 {
     if (dir != B64_DIR_ENCODE && dir != B64_DIR_DECODE) return b64i_fail(B64_BAD_ARG, "bad direction");
     if (N < 0 || !in_off || !out_off) return b64i_fail(B64_BAD_ARG, "bad offsets arguments");
-    Msgs msgs{in_off, nullptr};
-    hipLaunchKernelGGL(k_out_offsets, 1, 1024, 0, (hipStream_t)stream, dir, msgs, N, flags, out_off);
-    LAUNCH_TRY();
+    hipStream_t s = (hipStream_t)stream;
+    const Msgs msgs{in_off, nullptr};
+    const int64_t chunks = std::max<int64_t>(1, (N + PLAN_CHUNK - 1) / PLAN_CHUNK);
+    // partial sums in stream-ordered memory, so calls on several streams
+    // never share it
+    int64_t *partial = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&partial, 8 * chunks, s));
+    hipLaunchKernelGGL(k_out_reduce, (unsigned)chunks, PLAN_BLOCK, 0, s, dir, msgs, N, flags, partial);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_out_scan, (unsigned)chunks, PLAN_BLOCK, 0, s, dir, msgs, N, flags,
+                           (const int64_t *)partial, out_off);
+        e = hipGetLastError();
+    }
+    HIP_TRY(hipFreeAsync(partial, s));
+    if (e != hipSuccess) return b64i_fail(B64_HIP_ERROR, "kernel launch failed: %s", hipGetErrorString(e));
     return B64_OK;
 }
 

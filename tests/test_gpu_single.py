@@ -255,3 +255,32 @@ def test_table7_file_sizes_match_oracle():
         out, err = codec.decode(t)
         w = oracle.decode(want)
         assert err == -1 and out.numel() == w[0] and np.array_equal(out.cpu().numpy(), w[2]), name
+
+
+def test_single_buffer_beyond_4gib():
+    """5 GiB round trip (byte offsets above 2^32): decode(encode(x)) == x;
+    sampled 12-byte-aligned windows of the text equal the oracle's encoding
+    of the same bytes; an injected byte near the end is found at its index."""
+    n = 5 << 30
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    x = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda:0", generator=g)
+    t = codec.encode(x)
+    m = t.numel()
+    assert m == 4 * -(-n // 3)
+    rng = np.random.default_rng(11)
+    for start in list(rng.integers(0, n // 12 - 1000, 6) * 12) + [n // 12 * 12 - 12 * 100]:
+        xb = x[start:start + 1200].cpu().numpy()
+        want = oracle.encode(xb)
+        got = t[start // 3 * 4:start // 3 * 4 + want.size].cpu().numpy()
+        assert np.array_equal(got, want), start
+    start = (n - 12) // 3 * 3  # the last bytes, from a multiple of 3: the padded tail
+    want = oracle.encode(x[start:].cpu().numpy())
+    assert np.array_equal(t[start // 3 * 4:].cpu().numpy(), want)
+    out, err = codec.decode(t)
+    assert err == -1 and out.numel() == n and torch.equal(out, x)
+    del out
+    pos = m - 4097
+    t[pos] = ord("*")
+    out, err = codec.decode(t)
+    assert out is None and err == pos

@@ -276,3 +276,24 @@ def test_out_offsets_scan_sizes():
         we = np.zeros(N + 1, np.int64)
         np.cumsum(4 * ((lens + 2) // 3), out=we[1:])
         assert np.array_equal(e, we) and np.array_equal(d, dec_slots(off, fl))
+
+
+@pytest.mark.parametrize("alphabet", [0, 1])
+def test_rejection_sweep_as_one_batch(alphabet):
+    """All 256 byte values at 7 position classes (first, second, third,
+    interior, n-3, n-2, n-1 of a 96-character text) as 1,792 messages of one
+    batched decode: verdicts and bytes equal the oracle's per message."""
+    rng = np.random.default_rng(30 + alphabet)
+    base = oracle.encode(rng.integers(0, 256, 72, dtype=np.uint8), alphabet)
+    n = base.size
+    msgs = []
+    for v in range(256):
+        for pos in (0, 1, 2, 41, n - 3, n - 2, n - 1):
+            t = base.copy()
+            t[pos] = v
+            msgs.append(t)
+    text = np.concatenate(msgs)
+    toff = np.arange(len(msgs) + 1, dtype=np.int64) * n
+    flags = np.full(len(msgs), alphabet, np.uint8)
+    gl, ge = check_decode(text, toff, flags)
+    assert (ge >= 0).sum() > 1000

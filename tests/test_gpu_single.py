@@ -13,10 +13,14 @@ STD, URL = codec.ALPHABET_STD, codec.ALPHABET_URL
 NOPAD, STRICT = codec.MODE_NOPAD, codec.MODE_STRICT
 DEV = "cuda:0"
 
-# sizes around lane units (12 B / 16 chars), waves, default tiles
-# (256 lanes x 4 units) and a ragged tail
+# sizes around lane units (12 B / 16 chars), waves, the default tiles (encode
+# 512 lanes x 2 units = 12,288 B; decode 256 lanes x 2 units = 8,192
+# characters = 6,144 B), several tiles, the one-workgroup decode limit
+# (16,384 interior units = 262,144 characters = 196,608 B) and ragged tails
 SIZES = sorted(set(list(range(0, 70)) + [95, 96, 97, 767, 768, 769, 1023, 1024, 1025,
-                                         12287, 12288, 12289, 16383, 16384, 16385,
+                                         6143, 6144, 6145, 12287, 12288, 12289, 16383, 16384, 16385,
+                                         24575, 24576, 24577, 49151, 49152, 49153,
+                                         196_605, 196_606, 196_607, 196_608, 196_609, 196_611, 196_614,
                                          3 * 4096 * 4 + 5, 200_003, 1_000_001]))
 
 

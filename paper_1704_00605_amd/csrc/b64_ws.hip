@@ -183,42 +183,57 @@ __global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ 
         ws[3] = ERR_NONE;
     }
     const int64_t base = t * TILE;
-    uint32_t w[CPL][4];
+    uint32_t w[CPL][4], keep[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; k++) tile_load16<ALIGNED>(src, n, base + 16 * ((int64_t)k * BLOCK + tid), w[k]);
 #pragma unroll
     for (int k = 0; k < CPL; k++) {
-        const uint32_t keep = kept4(w[k][0]) | (kept4(w[k][1]) << 4) | (kept4(w[k][2]) << 8) | (kept4(w[k][3]) << 12);
-        const uint32_t c = __popc(keep);
+        keep[k] = kept4(w[k][0]) | (kept4(w[k][1]) << 4) | (kept4(w[k][2]) << 8) | (kept4(w[k][3]) << 12);
+        const uint32_t c = __popc(keep[k]);
         uint32_t tot = 0;
 #pragma unroll
         for (int b = 0; b < 5; b++) tot += (uint32_t)__popcll(__ballot((c >> b) & 1)) << b;
-        // last three kept bytes of the wave's segment: from its last lanes
-        // that keep anything (at most three of them), in scalar registers
-        unsigned long long nz = __ballot(c > 0);
-        uint32_t ac = 0, ar = 0;
-        while (nz && ac < 3) {
-            const int h = 63 - __clzll(nz);
-            uint32_t m = __builtin_amdgcn_readlane(keep, h);
-            const uint32_t x[4] = {(uint32_t)__builtin_amdgcn_readlane(w[k][0], h),
-                                   (uint32_t)__builtin_amdgcn_readlane(w[k][1], h),
-                                   (uint32_t)__builtin_amdgcn_readlane(w[k][2], h),
-                                   (uint32_t)__builtin_amdgcn_readlane(w[k][3], h)};
-            uint32_t car = 0, nc = 0;
-            while (m && nc < 3) {
-                const int j = 31 - __clz(m);
-                car |= ((x[j >> 2] >> (8 * (j & 3))) & 0xffu) << (8 * nc);
-                m &= ~(1u << j);
-                nc++;
+        if (lane == 0) s_cnt[k * NW + wid] = tot;
+    }
+    __syncthreads();
+    // the tile's last three kept bytes lie in its last (at most three)
+    // non-empty segments: only the waves holding those read them out of
+    // their lanes (scalar work, from the segment's last non-empty lanes)
+    int need = 3;
+    for (int i = E - 1; i >= 0 && need > 0; i--) {
+        const uint32_t cs = s_cnt[i];
+        if (cs == 0) continue;
+        if (i % NW == wid) {
+            const int ks = i / NW;
+#pragma unroll
+            for (int k = 0; k < CPL; k++) {
+                if (k != ks) continue;
+                const uint32_t c = __popc(keep[k]);
+                unsigned long long nz = __ballot(c > 0);
+                uint32_t ac = 0, ar = 0;
+                while (nz && ac < 3) {
+                    const int h = 63 - __clzll(nz);
+                    uint32_t m = __builtin_amdgcn_readlane(keep[k], h);
+                    const uint32_t x[4] = {(uint32_t)__builtin_amdgcn_readlane(w[k][0], h),
+                                           (uint32_t)__builtin_amdgcn_readlane(w[k][1], h),
+                                           (uint32_t)__builtin_amdgcn_readlane(w[k][2], h),
+                                           (uint32_t)__builtin_amdgcn_readlane(w[k][3], h)};
+                    const uint32_t cnt = __popc(m);
+                    uint32_t car = 0, nc = 0;
+                    while (m && nc < 3) {
+                        const int j = 31 - __clz(m);
+                        car |= ((x[j >> 2] >> (8 * (j & 3))) & 0xffu) << (8 * nc);
+                        m &= ~(1u << j);
+                        nc++;
+                    }
+                    ar = car_join(car, ar, ac);
+                    ac += cnt;
+                    nz &= ~(1ull << h);
+                }
+                if (lane == 0) s_car[i] = ar;
             }
-            ar = car_join(car, ar, ac);
-            ac += __popc(__builtin_amdgcn_readlane(keep, h));
-            nz &= ~(1ull << h);
         }
-        if (lane == 0) {
-            s_cnt[k * NW + wid] = tot;
-            s_car[k * NW + wid] = ar;
-        }
+        need -= (int)min(cs, 3u);
     }
     __syncthreads();
     if (tid == 0) {
@@ -226,6 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ 
         for (int i = 0; i < E; i++) cnt += s_cnt[i];
         uint32_t ac = 0, ar = 0;
         for (int i = E - 1; i >= 0 && ac < 3; i--) {
+            if (s_cnt[i] == 0) continue;
             ar = car_join(s_car[i], ar, ac);
             ac += s_cnt[i];
         }
@@ -434,26 +450,30 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     __syncthreads();
 
     // 4. decode the quads that end in this tile: stripped bytes
-    // [P - r0, P + ktot) sit at s_cls[16 - r0 ...]
+    // [P - r0, P + ktot) sit at s_cls[16 - r0 ...]; quad i of the tile
+    // (global quad qp + i) goes to dst + 3 * (qp + i). Units of four quads
+    // start at a global quad index divisible by 4, so their 12 output bytes
+    // are dword-aligned (with dst); a head unit takes the quads before the
+    // first such index.
     // quads ending in this tile; never past the output capacity 3 * (n / 4)
-    const int64_t qcap = n / 4 - (P - r0) / 4;
+    const int64_t qp = (P - r0) >> 2;
+    const int64_t qcap = n / 4 - qp;
     const int Q = (int)max((int64_t)0, min((int64_t)((r0 + (int)min(ktot, (uint32_t)TILE)) >> 2), qcap));
-    const int U = (Q + 3) >> 2;
-    uint8_t *q0 = dst + 3 * ((P - r0) >> 2);
+    const int hq = (int)((4 - (qp & 3)) & 3);
+    const int head = hq > 0 ? 1 : 0;
+    const int U = head + (Q > hq ? (Q - hq + 3) >> 2 : 0);
+    uint8_t *q0 = dst + 3 * qp;
+    const uint32_t sh = (uint32_t)((4 - r0) & 3);
     for (int u = tid; u < U; u += BLOCK) {
-        // 16 bytes from s_cls + 16 - r0 + 16u: the aligned chunk at 16u + 16
-        // and, when r0 > 0, the dword before it
-        uint32_t v0, v1, v2, v3;
-        const uint4 x = *(const uint4 *)(s_cls + 16 + 16 * u);
-        if (r0 == 0) {
-            v0 = x.x; v1 = x.y; v2 = x.z; v3 = x.w;
-        } else {
-            const uint32_t d0 = *(const uint32_t *)(s_cls + 12 + 16 * u);
-            const uint32_t sh = 4 - r0;
-            v0 = alignb(x.x, d0, sh); v1 = alignb(x.y, x.x, sh); v2 = alignb(x.z, x.y, sh); v3 = alignb(x.w, x.z, sh);
-        }
-        const int nq = min(4, Q - 4 * u);
-        uint8_t *q = q0 + 12 * (int64_t)u;
+        const int s0 = (head && u == 0) ? 0 : hq + 4 * (u - head);
+        const int nq = (head && u == 0) ? min(hq, Q) : min(4, Q - s0);
+        // 16 bytes from LDS byte 16 - r0 + 4 * s0 (dword-aligned part + shift)
+        const uint32_t *d = (const uint32_t *)(s_cls + ((16 - r0 + 4 * s0) & ~3));
+        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
+        const uint32_t d4 = sh ? d[4] : 0u;
+        uint32_t v0 = d0, v1 = d1, v2 = d2, v3 = d3;
+        if (sh) { v0 = alignb(d1, d0, sh); v1 = alignb(d2, d1, sh); v2 = alignb(d3, d2, sh); v3 = alignb(d4, d3, sh); }
+        uint8_t *q = q0 + 3 * (int64_t)s0;
         if (nq == 4 && !((v0 | v1 | v2 | v3) & 0x80808080u)) {
             const uint32_t t0 = quad_bits(v0), t1 = quad_bits(v1), t2 = quad_bits(v2), t3 = quad_bits(v3);
             const uint32_t o[3] = {perm(t1, t0, 0x06000102u), perm(t2, t1, 0x05060001u), perm(t3, t2, 0x04050600u)};

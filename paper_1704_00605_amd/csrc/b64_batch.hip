@@ -307,14 +307,20 @@ __device__ __forceinline__ void cursor_load(Cursor &c, const BatchArgs &a, int64
     c.fl = a.flags ? a.flags[m] : 0;
 }
 
-// Units gs + lane of one 64-unit group (gs < U); advances the cursor.
-__device__ __forceinline__ LaneRef resolve_group(Cursor &c, const BatchArgs &a, int64_t gs)
+// Moves the cursor to the message holding unit gs (gs < U, not before it).
+__device__ __forceinline__ void cursor_seek(Cursor &c, const BatchArgs &a, int64_t gs)
 {
     if (c.u1 <= gs) {  // the group starts in a later message
         int64_t m = c.m + 1;
         while (a.unit_off[m + 1] <= gs) m++;  // skips messages without units
         cursor_load(c, a, m);
     }
+}
+
+// Units gs + lane of one 64-unit group (gs < U); advances the cursor.
+__device__ __forceinline__ LaneRef resolve_group(Cursor &c, const BatchArgs &a, int64_t gs)
+{
+    cursor_seek(c, a, gs);
     const int64_t u = gs + __lane_id();
     if (gs + 64 <= c.u1) {  // whole group inside the cursor's message
         LaneRef r;
@@ -357,6 +363,23 @@ __global__ __launch_bounds__(1024) void k_enc_batch_w(
     Cursor c;
     cursor_load(c, a, wave_find_msg(unit_off, N, g0 * 64));
     for (int64_t g = g0; g < g1; g += UPL) {
+        // UPL whole groups of full units inside the cursor's message: the
+        // single-buffer step (no per-lane message lookup or tail branches)
+        if (g + UPL <= g1) {
+            const int64_t gs = g * 64;
+            cursor_seek(c, a, gs);
+            if (gs + 64 * UPL <= c.u0 + c.n / 12) {
+                const uint8_t *p = src + c.b;
+                uint8_t *q = dst + c.o;
+                const MapCtx mc{(const uint8_t *)s_tab + 64 * (c.fl & M_URL)};
+                const int64_t first = gs - c.u0 + __lane_id();
+                if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0)
+                    enc_step<true, UPL, false>(p, q, first, 64, 0, mc);
+                else
+                    enc_step<false, UPL, false>(p, q, first, 64, 0, mc);
+                continue;
+            }
+        }
         LaneRef r[UPL];
         uint32_t w[UPL][3];
         bool full[UPL];
@@ -393,6 +416,24 @@ __global__ __launch_bounds__(1024) void k_dec_batch_w(
     Cursor c;
     cursor_load(c, a, wave_find_msg(unit_off, N, g0 * 64));
     for (int64_t g = g0; g < g1; g += UPL) {
+        // UPL whole groups of interior units inside the cursor's message: the
+        // single-buffer step
+        if (g + UPL <= g1) {
+            const int64_t gs = g * 64;
+            cursor_seek(c, a, gs);
+            if (gs + 64 * UPL <= c.u0 + (c.n - 1) / 16) {
+                const uint8_t *p = src + c.b;
+                uint8_t *q = dst + c.o;
+                const MapCtx mc{(const uint8_t *)s_tab + 256 * (c.fl & M_URL)};
+                unsigned long long *slot = (unsigned long long *)&err_off[c.m];
+                const int64_t first = gs - c.u0 + __lane_id();
+                if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0)
+                    dec_step<true, UPL, false>(p, q, first, 64, 0, mc, slot);
+                else
+                    dec_step<false, UPL, false>(p, q, first, 64, 0, mc, slot);
+                continue;
+            }
+        }
         LaneRef r[UPL];
         uint32_t w[UPL][4];
         bool interior[UPL];

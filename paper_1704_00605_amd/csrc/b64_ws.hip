@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "b64.h"
@@ -534,8 +535,8 @@ namespace {
 constexpr int64_t WS_MIN_TILE = 256 * 16;
 
 struct WsShape {  // default: the fastest shape of a sweep on MI355X (MIME text, 1.47 GB)
-    int block = 256;
-    int cpl = 2;
+    std::atomic<int> block{256};
+    std::atomic<int> cpl{2};
 };
 WsShape g_ws;
 
@@ -567,7 +568,7 @@ int launch_ws(int block, int cpl, int64_t T, const uint8_t *src, int64_t n, uint
 int enqueue_ws(const uint8_t *src, int64_t n, uint8_t *dst, int alpha, int64_t *d_len, int64_t *d_err,
                unsigned long long *ws, hipStream_t s)
 {
-    const int block = g_ws.block, cpl = g_ws.cpl;
+    const int block = g_ws.block.load(), cpl = g_ws.cpl.load();
     const int64_t T = ws_tiles(n, (int64_t)block * 16 * cpl);
     const bool al = (((uintptr_t)src) & 3) == 0;
     int rc = al ? launch_ws<true>(block, cpl, T, src, n, dst, alpha, ws, s)
@@ -679,8 +680,8 @@ int64_t b64_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
 int b64_set_ws_tune(const b64_tune *t)
 {
     if (!t) return b64i_fail(B64_BAD_ARG, "null tune");
-    const int block = t->block ? t->block : g_ws.block;
-    const int cpl = t->units_per_lane ? t->units_per_lane : g_ws.cpl;
+    const int block = t->block ? t->block : g_ws.block.load();
+    const int cpl = t->units_per_lane ? t->units_per_lane : g_ws.cpl.load();
     const bool ok = (block == 256 && (cpl == 1 || cpl == 2 || cpl == 4 || cpl == 8)) ||
                     (block == 512 && (cpl == 1 || cpl == 2 || cpl == 4)) ||
                     (block == 1024 && (cpl == 1 || cpl == 2));

@@ -297,3 +297,41 @@ def test_rejection_sweep_as_one_batch(alphabet):
     flags = np.full(len(msgs), alphabet, np.uint8)
     gl, ge = check_decode(text, toff, flags)
     assert (ge >= 0).sum() > 1000
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_batch_misaligned_user_output_slots(layout):
+    """Caller-chosen output slots at any alignment (gaps of 0..3 bytes
+    between slots, destination view shifted by one byte): every message's
+    output equals the oracle's and no byte between slots is written."""
+    rng = np.random.default_rng(40 + layout)
+    N = 700
+    lens = np.where(rng.uniform(size=N) < 0.05, rng.integers(3000, 60_000, N), rng.integers(0, 400, N))
+    data, off = packed(lens, 40 + layout)
+    text, toff = encode_text(data, off)
+    for direction in (0, 1):
+        src, in_off = (data, off) if direction == 0 else (text, toff)
+        n_in = np.diff(in_off)
+        size = 4 * ((n_in + 2) // 3) if direction == 0 else 3 * (n_in // 4)
+        gap = rng.integers(0, 4, N)
+        out_off = np.zeros(N + 1, np.int64)
+        np.cumsum(size + gap, out=out_off[1:])
+        base = torch.full((int(out_off[-1]) + 8,), 0xAB, dtype=torch.uint8, device=DEV)
+        dst = base[1:]
+        oo = dev(out_off)
+        tune = dict(layout=layout)
+        if direction == 0:
+            codec.encode_batch(dev(src), dev(in_off), oo, dst=dst, tune=tune)
+            want, want_off, want_len = oracle.encode_batch(src, in_off)
+        else:
+            _, _, gl, ge = codec.decode_batch(dev(src), dev(in_off), oo, dst=dst, tune=tune)
+            want, want_off, want_len, want_err = oracle.decode_batch(src, in_off)
+            assert np.array_equal(host(gl), want_len) and np.array_equal(host(ge), want_err)
+        got = host(dst)
+        for i in range(N):
+            L = int(want_len[i])
+            if L > 0:
+                assert np.array_equal(got[out_off[i]:out_off[i] + L], want[want_off[i]:want_off[i] + L]), (direction, i)
+            # the gap after the slot's capacity is untouched
+            assert (got[out_off[i] + size[i]:out_off[i + 1]] == 0xAB).all(), (direction, i)
+        assert host(base)[0] == 0xAB

@@ -3,21 +3,22 @@
 // (include/b64.h). The input is cut into tiles of blockDim * 4 * CPL bytes.
 //
 //   k_ws_count    per tile: number of kept (non-whitespace) bytes and the
-//                 last three of them, from SWAR whitespace tests; also resets
-//                 the error slots.
+//                 last three of them, from SWAR whitespace tests, and a flag
+//                 for control bytes that are not whitespace; also resets the
+//                 error slots.
 //   k_ws_reduce   per group of 2048 tiles: the ordered combination of their
 //                 (count, last three) states.
 //   k_ws_prefix   per tile: the exclusive prefix state, i.e. the stripped
 //                 offset P of the tile's first kept byte and the three kept
 //                 bytes just before it (an ordered scan; the operator keeps
 //                 counts and the last three bytes, so it is associative).
-//   k_dec_ws      per tile: classify every byte through one LDS table
-//                 (symbol value, '=', whitespace, invalid), compact the kept
-//                 class bytes into LDS with ballot + mbcnt prefix counts, put
-//                 the carried bytes of the quad that straddles into the tile
-//                 in front, report invalid bytes and '=' in original
-//                 coordinates, and decode every quad of the stripped text that
-//                 ends in this tile (its bytes go to 3 * quad index).
+//   k_dec_ws      per tile: compact the kept bytes into LDS (DPP wave scan
+//                 of per-dword counts), put the carried bytes of the quad
+//                 that straddles into the tile in front, decode every quad of
+//                 the stripped text that ends in this tile through one LDS
+//                 class table (its bytes go to 3 * quad index), and, when a
+//                 mark (invalid byte, '=') turns up, rescan the raw tile to
+//                 report it in original coordinates.
 //   k_dec_ws_final verdict from the total state and the error slots.
 //
 // Two passes read the input (count, then decode) and no tile waits for
@@ -89,7 +90,13 @@ __device__ __forceinline__ uint32_t car_join(uint32_t a, uint32_t b, uint64_t nb
 // State of run a followed by run b.
 __device__ __forceinline__ WsSt st_join(WsSt a, WsSt b) { return {a.c + b.c, car_join(a.r, b.r, b.c)}; }
 __device__ __forceinline__ unsigned long long st_pack(WsSt s) { return (s.c << 24) | (s.r & 0xffffffu); }
-__device__ __forceinline__ WsSt st_unpack(unsigned long long w) { return {w >> 24, (uint32_t)(w & 0xffffffu)}; }
+__device__ __forceinline__ WsSt st_unpack(unsigned long long w)
+{
+    return {(w >> 24) & (uint64_t)WS_MAX_N, (uint32_t)(w & 0xffffffu)};
+}
+// Bit 63 of a tile's state word (not part of the state): the tile holds a
+// byte at or below 0x20 that is not whitespace.
+constexpr unsigned long long WS_CTRL_FLAG = 1ull << 63;
 
 __device__ __forceinline__ WsSt shfl_up_st(WsSt s, int d)
 {
@@ -154,16 +161,31 @@ __device__ __forceinline__ void tile_load16(const uint8_t *__restrict__ src, int
     }
 }
 
-// 4-bit mask of the bytes of w that are kept: those above 0x20. On a valid
-// input every byte at or below 0x20 is space, LF or CR, so this removes
-// exactly the whitespace; on an invalid input the verdict does not depend on
-// the counts (see k_dec_ws_final), and invalid bytes are still found by
-// their class.
-__device__ __forceinline__ uint32_t kept4(uint32_t w)
+// Kept bytes of w: bit 8j+7 set when byte j is above 0x20. On a valid input
+// every byte at or below 0x20 is space, LF or CR, so this removes exactly the
+// whitespace. Other bytes at or below 0x20 are invalid: the count pass flags
+// their tiles (ctrl_bad), and on an invalid input the verdict does not depend
+// on the counts (see k_dec_ws_final).
+__device__ __forceinline__ uint32_t kept8(uint32_t w)
 {
-    const uint32_t x = (((w & 0x7f7f7f7fu) + 0x5f5f5f5fu) | w) & 0x80808080u;  // bit 8j+7: byte j > 0x20
-    const uint32_t y = x >> 7;
-    return (y | (y >> 7) | (y >> 14) | (y >> 21)) & 0xf;
+    return (((w & 0x7f7f7f7fu) + 0x5f5f5f5fu) | w) & 0x80808080u;
+}
+
+// Bit 8j+7 set when byte j of w is at or below 0x20 and is not space (0x20),
+// LF (0x0A) or CR (0x0D). The byte permute serves as a lookup keyed by the
+// byte values themselves: selectors 13 and above give 0xff, 12 gives 0,
+// 10 copies the sign of table byte 5 (set), and 0..9 and 11 give table bytes
+// or signs whose bit 0 is clear; so bit 0 of the result is set exactly for
+// 10 and for 13 and above. Values 14..31 are then excluded by a compare, and
+// 32 is admitted by its bit 5.
+__device__ __forceinline__ uint32_t ctrl_bad(uint32_t w)
+{
+    const uint32_t xm = w & 0x7f7f7f7fu;
+    const uint32_t kept = ((xm + 0x5f5f5f5fu) | w) & 0x80808080u;
+    const uint32_t ge14 = xm + 0x72727272u;  // bit 8j+7: (byte j & 0x7f) >= 14
+    const uint32_t p = perm(0x00008000u, 0u, w);
+    const uint32_t ok = (w << 2) | (~ge14 & (p << 7));
+    return ~kept & ~ok & 0x80808080u;
 }
 
 // Tile = BLOCK * 16 * CPL bytes; lane tid reads the 16-byte chunks
@@ -184,16 +206,19 @@ __global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ 
         ws[3] = ERR_NONE;
     }
     const int64_t base = t * TILE;
-    uint32_t w[CPL][4], keep[CPL];
+    uint32_t w[CPL][4], cnt[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; k++) tile_load16<ALIGNED>(src, n, base + 16 * ((int64_t)k * BLOCK + tid), w[k]);
+    // per segment: kept bytes, and bit 31 when it holds a control byte that
+    // is not whitespace
 #pragma unroll
     for (int k = 0; k < CPL; k++) {
-        keep[k] = kept4(w[k][0]) | (kept4(w[k][1]) << 4) | (kept4(w[k][2]) << 8) | (kept4(w[k][3]) << 12);
-        const uint32_t c = __popc(keep[k]);
-        uint32_t tot = 0;
+        cnt[k] = __popc(kept8(w[k][0])) + __popc(kept8(w[k][1])) + __popc(kept8(w[k][2])) +
+                 __popc(kept8(w[k][3]));
+        const uint32_t bad = ctrl_bad(w[k][0]) | ctrl_bad(w[k][1]) | ctrl_bad(w[k][2]) | ctrl_bad(w[k][3]);
+        uint32_t tot = __ballot(bad != 0) ? 0x80000000u : 0u;
 #pragma unroll
-        for (int b = 0; b < 5; b++) tot += (uint32_t)__popcll(__ballot((c >> b) & 1)) << b;
+        for (int b = 0; b < 5; b++) tot += (uint32_t)__popcll(__ballot((cnt[k] >> b) & 1)) << b;
         if (lane == 0) s_cnt[k * NW + wid] = tot;
     }
     __syncthreads();
@@ -202,33 +227,36 @@ __global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ 
     // their lanes (scalar work, from the segment's last non-empty lanes)
     int need = 3;
     for (int i = E - 1; i >= 0 && need > 0; i--) {
-        const uint32_t cs = s_cnt[i];
+        const uint32_t cs = s_cnt[i] & 0x7fffffffu;
         if (cs == 0) continue;
         if (i % NW == wid) {
             const int ks = i / NW;
 #pragma unroll
             for (int k = 0; k < CPL; k++) {
                 if (k != ks) continue;
-                const uint32_t c = __popc(keep[k]);
-                unsigned long long nz = __ballot(c > 0);
+                unsigned long long nz = __ballot(cnt[k] > 0);
                 uint32_t ac = 0, ar = 0;
                 while (nz && ac < 3) {
                     const int h = 63 - __clzll(nz);
-                    uint32_t m = __builtin_amdgcn_readlane(keep[k], h);
                     const uint32_t x[4] = {(uint32_t)__builtin_amdgcn_readlane(w[k][0], h),
                                            (uint32_t)__builtin_amdgcn_readlane(w[k][1], h),
                                            (uint32_t)__builtin_amdgcn_readlane(w[k][2], h),
                                            (uint32_t)__builtin_amdgcn_readlane(w[k][3], h)};
-                    const uint32_t cnt = __popc(m);
+                    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane(cnt[k], h);
+                    // its last (up to three) kept bytes, from the top word down
                     uint32_t car = 0, nc = 0;
-                    while (m && nc < 3) {
-                        const int j = 31 - __clz(m);
-                        car |= ((x[j >> 2] >> (8 * (j & 3))) & 0xffu) << (8 * nc);
-                        m &= ~(1u << j);
-                        nc++;
+#pragma unroll
+                    for (int i = 3; i >= 0; i--) {
+                        uint32_t m = kept8(x[i]);
+                        while (m && nc < 3) {
+                            const int hb = 31 - __clz(m);  // bit 8j+7 of byte j
+                            car |= ((x[i] >> (hb - 7)) & 0xffu) << (8 * nc);
+                            m &= ~(1u << hb);
+                            nc++;
+                        }
                     }
                     ar = car_join(car, ar, ac);
-                    ac += cnt;
+                    ac += c;
                     nz &= ~(1ull << h);
                 }
                 if (lane == 0) s_car[i] = ar;
@@ -239,14 +267,19 @@ __global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ 
     __syncthreads();
     if (tid == 0) {
         uint64_t cnt = 0;
-        for (int i = 0; i < E; i++) cnt += s_cnt[i];
+        uint32_t ctrl = 0;
+        for (int i = 0; i < E; i++) {
+            cnt += s_cnt[i] & 0x7fffffffu;
+            ctrl |= s_cnt[i];
+        }
         uint32_t ac = 0, ar = 0;
         for (int i = E - 1; i >= 0 && ac < 3; i--) {
-            if (s_cnt[i] == 0) continue;
+            const uint32_t cs = s_cnt[i] & 0x7fffffffu;
+            if (cs == 0) continue;
             ar = car_join(s_car[i], ar, ac);
-            ac += s_cnt[i];
+            ac += cs;
         }
-        ws[WS_SLOT_WORDS + t] = st_pack({cnt, ar});
+        ws[WS_SLOT_WORDS + t] = st_pack({cnt, ar}) | ((ctrl >> 31) ? WS_CTRL_FLAG : 0ull);
     }
 }
 
@@ -328,9 +361,12 @@ __device__ __forceinline__ uint32_t quad_bits(uint32_t v)
 }
 
 // Tile = BLOCK * 16 * CPL bytes, loaded as 16-byte chunks (k * BLOCK + tid)
-// and staged in LDS; classification and compaction then work on dwords
+// and staged in LDS; counting and compaction then work on dwords
 // d = k2 * BLOCK + tid (k2 < 4 * CPL), so that lanes touch consecutive LDS
-// words and memory order is (k2, wave, lane, byte).
+// words and memory order is (k2, wave, lane, byte). The raw kept bytes are
+// compacted; symbol values are looked up only when the quads are decoded, and
+// marks (invalid bytes, '=') send the tile through a rescan of its raw bytes
+// that reports them in original coordinates.
 template <int BLOCK, int CPL, bool ALIGNED>
 __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ src, int64_t n,
                                                   uint8_t *__restrict__ dst, int alpha,
@@ -342,12 +378,18 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     constexpr int E = K2 * NW;              // (k2, wave) segments
     static_assert(E <= 128, "segment scan covers at most 128 entries");
     __shared__ uint32_t s_tab[64];
-    __shared__ __attribute__((aligned(16))) uint32_t s_raw[TILE / 4];  // raw tile
-    __shared__ __attribute__((aligned(16))) uint8_t s_cls[16 + TILE + 16];
-    __shared__ uint32_t s_seg[E];          // kept bytes per segment, then their exclusive prefix
-    __shared__ uint32_t s_tot;
+    __shared__ __attribute__((aligned(16))) uint32_t s_raw[TILE / 4];      // raw tile
+    // stripped text, from byte F - r0 (F in [16, 32), chosen per tile so that
+    // every unit of four quads after the head starts on a 16-byte boundary),
+    // with tail room for the last unit's read past a partial quad
+    __shared__ uint4 s_txt4[(32 + TILE + 32) / 16];
+    uint8_t *const s_txt = (uint8_t *)s_txt4;
+    __shared__ uint32_t s_seg[E];          // kept bytes per segment
+    __shared__ uint32_t s_pre[E];          // their exclusive prefix
 
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+    lds_fill(s_tab, c_ws.cls[alpha], 256);
+    const uint8_t *tab = (const uint8_t *)s_tab;
     const int64_t t = blockIdx.x;
     const int64_t base = t * TILE;
     {
@@ -358,21 +400,25 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
         for (int k = 0; k < CPL; k++)
             *(uint4 *)&s_raw[4 * (k * BLOCK + tid)] = make_uint4(w[k][0], w[k][1], w[k][2], w[k][3]);
     }
-    // exclusive prefix: stripped offset of the tile's first kept byte and the
-    // kept bytes before it
+    // the tile's own state (flag: a control byte other than whitespace) and
+    // its exclusive prefix: stripped offset of the tile's first kept byte and
+    // the kept bytes before it
+    const unsigned long long own = ws[WS_SLOT_WORDS + t];
     const WsSt pf = st_unpack(ws[WS_SLOT_WORDS + T + t]);
     const int64_t P = (int64_t)pf.c;
     const int r0 = (int)(P & 3);
-    lds_fill(s_tab, c_ws.cls[alpha], 256);
+    // the tile's first quad is global quad qp; hq quads precede the first
+    // global quad index divisible by 4 (where the units of four quads start)
+    const int64_t qp = (P - r0) >> 2;
+    const int hq = (int)((4 - (qp & 3)) & 3);
+    const int F = 16 + ((r0 - 4 * hq) & 15);  // F - r0 + 4 * hq is a multiple of 16
+    if (tid < r0) s_txt[F - r0 + tid] = (uint8_t)(pf.r >> (8 * (r0 - 1 - tid)));
     __syncthreads();
-    const uint8_t *tab = (const uint8_t *)s_tab;
-    if (tid < r0) s_cls[16 - r0 + tid] = tab[(pf.r >> (8 * (r0 - 1 - tid))) & 0xff];
 
-    // 1. classify and count kept bytes;
-    // per-lane exclusive prefixes within the wave from one DPP scan per three
-    // dwords (10-bit fields: a wave keeps at most 256 bytes of a dword row)
-    uint32_t pre[K2], keepm[K2], clsm[K2];
-    uint32_t spec = 0;
+    // 1. kept bytes per dword; per-lane exclusive prefixes within the wave
+    // from one DPP scan per three dwords (10-bit fields: a wave keeps at most
+    // 256 bytes of a dword row)
+    uint32_t xs[K2], keepm[K2], pre[K2];
 #pragma unroll
     for (int k0 = 0; k0 < K2; k0 += 3) {
         uint32_t packed = 0;
@@ -380,14 +426,9 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
         for (int i = 0; i < 3; i++) {
             const int k = k0 + i;
             if (k < K2) {
-                const uint32_t x = s_raw[k * BLOCK + tid];
-                const uint32_t c = tab[x & 0xff] | ((uint32_t)tab[(x >> 8) & 0xff] << 8) |
-                                   ((uint32_t)tab[(x >> 16) & 0xff] << 16) | ((uint32_t)tab[x >> 24] << 24);
-                clsm[k] = c;
-                const uint32_t keep = kept4(x);
-                keepm[k] = keep;
-                spec |= c & ~(c << 1) & 0x80808080u;  // bit 7 set, bit 6 clear: invalid or '='
-                packed |= (uint32_t)__popc(keep) << (10 * i);
+                xs[k] = s_raw[k * BLOCK + tid];
+                keepm[k] = kept8(xs[k]);
+                packed |= (uint32_t)__popc(keepm[k]) << (10 * i);
             }
         }
         const uint32_t inc = wave_incl_sum(packed);
@@ -403,95 +444,146 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
         }
     }
     __syncthreads();
-    // 2. exclusive prefix over the (k2, wave) segments
-    if (wid == 0) {
+    // 2. exclusive prefix over the (k2, wave) segments, computed by every
+    // wave for its own segments (no barrier), and the tile's kept total
+    uint32_t segpre[K2];
+    uint32_t ktot;
+    {
         const uint32_t a0 = 2 * lane < E ? s_seg[2 * lane] : 0u;
         const uint32_t a1 = 2 * lane + 1 < E ? s_seg[2 * lane + 1] : 0u;
-        const uint32_t own = a0 + a1;
-        uint32_t inc = own;
+        const uint32_t pair = a0 + a1;
+        const uint32_t inc = wave_incl_sum(pair);
+        const uint32_t ex = inc - pair;  // prefix of segment 2 * lane
+        ktot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += y;
+        for (int k = 0; k < K2; k++) {
+            const int e = k * NW + wid;
+            const uint32_t ex2 = (uint32_t)__builtin_amdgcn_readlane((int)ex, e >> 1);
+            const uint32_t a02 = (uint32_t)__builtin_amdgcn_readlane((int)a0, e >> 1);
+            segpre[k] = (e & 1) ? ex2 + a02 : ex2;
+            if (lane == 0) s_pre[e] = segpre[k];
         }
-        const uint32_t ex = inc - own;
-        if (2 * lane < E) s_seg[2 * lane] = ex;
-        if (2 * lane + 1 < E) s_seg[2 * lane + 1] = ex + a0;
-        if (lane == 63) s_tot = inc;
     }
-    __syncthreads();
 
-    // 3. compaction: kept class bytes to s_cls[16 + tile-stripped index];
-    // invalid bytes and '=' reported in original coordinates (rare)
-    const bool rare = __ballot(spec != 0) != 0;
+    // 3. compaction: kept raw bytes to s_txt[F + tile-stripped index]
 #pragma unroll
     for (int k = 0; k < K2; k++) {
-        const uint32_t c = clsm[k];
-        const uint32_t keep = keepm[k];  // bytes above 0x20
-        const uint32_t at = s_seg[k * NW + wid] + pre[k];
-        uint32_t pos = 16 + at;
+        const uint32_t x = xs[k], keep = keepm[k];
+        uint32_t pos = F + segpre[k] + pre[k];
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if ((keep >> j) & 1) s_cls[pos++] = (uint8_t)(c >> (8 * j));
-        if (rare) {
-            const int64_t off = base + 4 * ((int64_t)k * BLOCK + tid);
-            uint32_t rank = 0;
-            for (int j = 0; j < 4; j++) {
-                const uint32_t cb = (c >> (8 * j)) & 0xff;
-                if (cb == C_BAD) atomicMin(&ws[1], (unsigned long long)(off + j));
-                if (cb == C_PAD) {
-                    atomicMin(&ws[2], (unsigned long long)(off + j));
-                    atomicMin(&ws[3], (unsigned long long)(P + at + rank));
-                }
-                rank += (keep >> j) & 1;
-            }
-        }
+            if (keep & (0x80u << (8 * j))) s_txt[pos++] = (uint8_t)(x >> (8 * j));
     }
-    const uint32_t ktot = s_tot;
     __syncthreads();
 
     // 4. decode the quads that end in this tile: stripped bytes
-    // [P - r0, P + ktot) sit at s_cls[16 - r0 ...]; quad i of the tile
+    // [P - r0, P + ktot) sit at s_txt[F - r0 ...]; quad i of the tile
     // (global quad qp + i) goes to dst + 3 * (qp + i). Units of four quads
     // start at a global quad index divisible by 4, so their 12 output bytes
     // are dword-aligned (with dst); a head unit takes the quads before the
-    // first such index.
-    // quads ending in this tile; never past the output capacity 3 * (n / 4)
-    const int64_t qp = (P - r0) >> 2;
-    const int64_t qcap = n / 4 - qp;
-    const int Q = (int)max((int64_t)0, min((int64_t)((r0 + (int)min(ktot, (uint32_t)TILE)) >> 2), qcap));
-    const int hq = (int)((4 - (qp & 3)) & 3);
+    // first such index. Every kept byte is looked up, including those of a
+    // trailing partial quad (decoded by the next tile, or left over at the end
+    // of the text), so that each mark is seen by the tile that holds it.
+    const int L = r0 + (int)min(ktot, (uint32_t)TILE);  // stripped bytes here
+    const int64_t qcap = n / 4 - qp;                    // never past 3 * (n / 4)
+    const int Q = (int)max((int64_t)0, min((int64_t)(L >> 2), qcap));  // quads decoded
+    const int QC = (L + 3) >> 2;                                         // quads checked
     const int head = hq > 0 ? 1 : 0;
-    const int U = head + (Q > hq ? (Q - hq + 3) >> 2 : 0);
+    const int U = head + (QC > hq ? (QC - hq + 3) >> 2 : 0);
     uint8_t *q0 = dst + 3 * qp;
-    const uint32_t sh = (uint32_t)((4 - r0) & 3);
+    bool mark = false;
     for (int u = tid; u < U; u += BLOCK) {
-        const int s0 = (head && u == 0) ? 0 : hq + 4 * (u - head);
-        const int nq = (head && u == 0) ? min(hq, Q) : min(4, Q - s0);
-        // 16 bytes from LDS byte 16 - r0 + 4 * s0 (dword-aligned part + shift)
-        const uint32_t *d = (const uint32_t *)(s_cls + ((16 - r0 + 4 * s0) & ~3));
-        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
-        const uint32_t d4 = sh ? d[4] : 0u;
-        uint32_t v0 = d0, v1 = d1, v2 = d2, v3 = d3;
-        if (sh) { v0 = alignb(d1, d0, sh); v1 = alignb(d2, d1, sh); v2 = alignb(d3, d2, sh); v3 = alignb(d4, d3, sh); }
+        const bool hd = head && u == 0;
+        const int s0 = hd ? 0 : hq + 4 * (u - head);
+        const int nq = hd ? min(hq, Q) : min(4, Q - s0);           // quads to decode (may be <= 0)
+        const int nb = min(hd ? 4 * hq : 16, L - 4 * s0);         // bytes to look up
+        // 16 bytes from LDS byte F - r0 + 4 * s0 in one aligned read; the
+        // head unit starts 4 * hq bytes before a 16-byte boundary, so its
+        // quads are the last hq dwords of the chunk read
+        const uint4 c = s_txt4[(F - r0 + 4 * s0) >> 4];
+        uint32_t vs[4] = {c.x, c.y, c.z, c.w};
+        if (hd) {
+            if (hq == 1) {
+                vs[0] = c.w;
+            } else if (hq == 2) {
+                vs[0] = c.z;
+                vs[1] = c.w;
+            } else {
+                vs[0] = c.y;
+                vs[1] = c.z;
+                vs[2] = c.w;
+            }
+        }
         uint8_t *q = q0 + 3 * (int64_t)s0;
-        if (nq == 4 && !((v0 | v1 | v2 | v3) & 0x80808080u)) {
-            const uint32_t t0 = quad_bits(v0), t1 = quad_bits(v1), t2 = quad_bits(v2), t3 = quad_bits(v3);
-            const uint32_t o[3] = {perm(t1, t0, 0x06000102u), perm(t2, t1, 0x05060001u), perm(t3, t2, 0x04050600u)};
-            store_words<3, true>(q, o);
-        } else {
-            // a partial unit, or marks: '=' counts as 0 and the bytes it pads
-            // are not written (any other placement is an error, and the
-            // output of an invalid input is unspecified)
-            const uint32_t vs[4] = {v0, v1, v2, v3};
-            for (int i = 0; i < nq; i++) {
-                const uint32_t v = vs[i];
-                const uint32_t c2 = (v >> 16) & 0xff, c3 = v >> 24;
-                const uint32_t mk = v & 0x80808080u;
-                const uint32_t tq = quad_bits(v & ~(mk >> 2) & ~mk);
-                q[3 * i] = (uint8_t)(tq >> 16);
-                if (!(c2 == C_PAD && c3 == C_PAD)) q[3 * i + 1] = (uint8_t)(tq >> 8);
-                if (c3 != C_PAD) q[3 * i + 2] = (uint8_t)tq;
+        if (nq == 4) {
+            uint32_t tq[4], mk = 0;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const uint32_t a = tab[vs[i] & 0xff], b = tab[(vs[i] >> 8) & 0xff];
+                const uint32_t c = tab[(vs[i] >> 16) & 0xff], e = tab[vs[i] >> 24];
+                mk |= a | b | c | e;
+                tq[i] = (a << 18) | (b << 12) | (c << 6) | e;
+            }
+            if (!(mk & 0x80u)) {
+                const uint32_t o[3] = {perm(tq[1], tq[0], 0x06000102u), perm(tq[2], tq[1], 0x05060001u),
+                                       perm(tq[3], tq[2], 0x04050600u)};
+                store_words<3, true>(q, o);
+                continue;
+            }
+        }
+        // a partial unit, or marks: '=' counts as 0 and the bytes it pads are
+        // not written (any other placement is an error, and the output of an
+        // invalid input is unspecified)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (4 * i < nb) {
+                uint32_t cv = 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (4 * i + j < nb) cv |= (uint32_t)tab[(vs[i] >> (8 * j)) & 0xff] << (8 * j);
+                const uint32_t mk = cv & 0x80808080u;
+                mark |= mk != 0;
+                if (i < nq) {
+                    const uint32_t c2 = (cv >> 16) & 0xff, c3 = cv >> 24;
+                    const uint32_t tv = quad_bits(cv & ~(mk >> 2) & ~mk);
+                    q[3 * i] = (uint8_t)(tv >> 16);
+                    if (!(c2 == C_PAD && c3 == C_PAD)) q[3 * i + 1] = (uint8_t)(tv >> 8);
+                    if (c3 != C_PAD) q[3 * i + 2] = (uint8_t)tv;
+                }
+            }
+        }
+    }
+
+    // 5. invalid bytes and '=' in original coordinates (rare): a wave that
+    // looked up a mark rescans the whole raw tile through the class table
+    // (the mark may sit in any wave's raw segment), as does wave 0 when the
+    // count pass flagged a control byte in this tile. The first mark of each
+    // kind per lane and dword goes to its slot.
+    if (__ballot(mark) != 0 || (wid == 0 && (own & WS_CTRL_FLAG))) {
+#pragma unroll 1
+        for (int e = 0; e < E; e++) {
+            const int dw = (e / NW) * BLOCK + (e % NW) * 64 + lane;  // raw dword
+            const uint32_t x = s_raw[dw];
+            const uint32_t keep = kept8(x);
+            const uint32_t c = __popc(keep);
+            const int64_t at = P + s_pre[e] + (wave_incl_sum(c) - c);
+            const int64_t off = base + 4 * (int64_t)dw;
+            unsigned long long eb = ERR_NONE, eo = ERR_NONE, es = ERR_NONE;
+            uint32_t rank = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t cb = tab[(x >> (8 * j)) & 0xff];
+                if (cb == C_BAD && eb == ERR_NONE) eb = (unsigned long long)(off + j);
+                if (cb == C_PAD && eo == ERR_NONE) {
+                    eo = (unsigned long long)(off + j);
+                    es = (unsigned long long)(at + rank);
+                }
+                rank += (keep >> (8 * j + 7)) & 1;
+            }
+            if (eb != ERR_NONE) atomicMin(&ws[1], eb);
+            if (eo != ERR_NONE) {
+                atomicMin(&ws[2], eo);
+                atomicMin(&ws[3], es);
             }
         }
     }

@@ -196,3 +196,42 @@ def test_ws_mime_1gib_properties():
     del out
     out, err = codec.decode_ws(wrapped)
     assert out is None and err == p
+
+
+def test_ws_every_control_byte_is_an_error():
+    """Bytes at or below 0x20 other than space, LF and CR are invalid
+    (Appendix B removes only those three): each one, at random places of a
+    multi-tile text without padding, is reported at its own index."""
+    rng = np.random.default_rng(7)
+    text = oracle.encode(rng.integers(0, 256, 60_000, dtype=np.uint8))
+    a, _ = workloads.wrap_lines(text, 76, b"\r\n")
+    for shape in ((256, 1), (256, 2)):
+        codec.set_ws_tune(*shape)
+        for b in range(0x21):
+            if b in (0x0A, 0x0D, 0x20):
+                continue
+            for _ in range(3):
+                c = a.copy()
+                j = int(rng.integers(0, a.size))
+                c[j] = b
+                assert check(c)[:2] == (-1, j), (shape, b, j)
+
+
+@pytest.mark.parametrize("shape", [(256, 1), (512, 2)])
+def test_ws_marks_next_to_tile_boundaries(shape):
+    """Invalid bytes and '=' just before and after tile boundaries, where the
+    last kept bytes of a tile form a partial quad that the next tile decodes."""
+    codec.set_ws_tune(*shape)
+    tile = shape[0] * 16 * shape[1]
+    rng = np.random.default_rng(8)
+    text = oracle.encode(rng.integers(0, 256, 5 * tile, dtype=np.uint8))
+    a, _ = workloads.sprinkle_ws(rng, text, 0.03)
+    for t in range(1, a.size // tile):
+        for d in range(-5, 5):
+            j = t * tile + d
+            if a[j] in workloads.WS_BYTES:
+                continue
+            for bad in (ord("*"), ord("="), 0x80):
+                c = a.copy()
+                c[j] = bad
+                check(c)

@@ -483,9 +483,17 @@ template <int UPL, class Fast, class General>
 __device__ __forceinline__ void batch_tiles(const BatchArgs &a, Fast fast, General general, bool decode)
 {
     const int64_t tile = (int64_t)blockDim.x * UPL;
-    int64_t m = 0;
-    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < a.U; t0 += (int64_t)gridDim.x * tile) {
-        m = block_find_msg(a.unit_off, a.N, t0, m);
+    const int64_t stride = (int64_t)gridDim.x * tile;
+    int64_t t0 = (int64_t)blockIdx.x * tile;
+    if (t0 >= a.U) return;
+    int64_t m = block_find_msg(a.unit_off, a.N, t0, 0);
+    for (; t0 < a.U; t0 += stride) {
+        // The next tile's search starts here: every thread probes one of the
+        // blockDim.x messages after m against the next tile's first unit, and
+        // the probe loads stay in flight while this tile is worked on.
+        const int64_t tn = t0 + stride;
+        const int64_t pi = m + 1 + threadIdx.x;
+        const int ok = tn < a.U && pi < a.N && a.unit_off[pi] <= tn;
         const int64_t t1 = min(t0 + tile, a.U);
         const int64_t u0 = a.unit_off[m];
         const int64_t n = a.msgs.n(m);
@@ -498,6 +506,11 @@ __device__ __forceinline__ void batch_tiles(const BatchArgs &a, Fast fast, Gener
 #pragma unroll 1
             for (int k = 0; k < UPL; k++) general(m, t0 + (int64_t)k * blockDim.x + threadIdx.x);
         }
+        // unit_off does not decrease, so the probes hold for a prefix: the
+        // next tile's first message is m + (their count), unless all of them
+        // hold (then a full search above the window)
+        const int64_t cnt = __syncthreads_count(ok);
+        m = cnt < (int64_t)blockDim.x ? m + cnt : block_find_msg(a.unit_off, a.N, tn, m + blockDim.x);
     }
 }
 

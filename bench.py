@@ -202,15 +202,7 @@ def main():
     # dominant kernel: the one with the largest share of the step (decode runs twice)
     dominant = "decode" if 2 * dec_ms >= enc_ms else "encode"
     ach = dec_bw if dominant == "decode" else enc_bw
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tf = json.load(open(TRAFFIC_FILE))
-            entry = tf.get(dominant)
-            if entry and entry.get("size") == n and entry.get("kernel_hash") == kernel_hash():
-                traffic = entry.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = stored_traffic(dominant, n)
     line = {
         "metric": METRIC,
         "value": round((n + 2 * m) / (step_ms * 1e-3) / 1e9, 3),
@@ -621,6 +613,20 @@ def report_serving(seconds):
     del pool, banks
     torch.cuda.empty_cache()
     return summ
+
+
+def stored_traffic(direction, n):
+    """HBM bytes per launch of the single-buffer kernel of `direction`, from
+    the committed counter summary, or None when that summary was taken on
+    another size or on other kernel sources."""
+    try:
+        tf = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    entry = tf.get(direction)
+    if not entry or tf.get("size") != n or tf.get("kernel_hash") != kernel_hash():
+        return None
+    return entry.get("bytes_per_launch")
 
 
 def kernel_hash():

@@ -409,23 +409,20 @@ int b64_set_single_tune(int dir, const b64_tune *t)
 {
     if (dir != 0 && dir != 1) return b64i_fail(B64_BAD_ARG, "bad direction");
     if (!t) return b64i_fail(B64_BAD_ARG, "null tune");
-    if (t->block) {
-        if (t->block < 64 || t->block > 1024 || (t->block & 63)) return b64i_fail(B64_BAD_ARG, "bad block");
-        g_single[dir].block = t->block;
-    }
-    if (t->units_per_lane) {
-        if (t->units_per_lane != 1 && t->units_per_lane != 2 && t->units_per_lane != 4 &&
-            t->units_per_lane != 8)
-            return b64i_fail(B64_BAD_ARG, "units_per_lane must be 1, 2, 4 or 8");
-        g_single[dir].upl = t->units_per_lane;
-    }
-    if (t->grid) {
-        // blocks per CU; -1 selects one workgroup per tile
-        if (t->grid < -1 || t->grid > 4096) return b64i_fail(B64_BAD_ARG, "blocks per CU must be -1 or 1..4096");
-        g_single[dir].blocks_per_cu = t->grid < 0 ? 0 : t->grid;
-    }
+    // every field is checked before any is applied
+    if (t->block && (t->block < 64 || t->block > 1024 || (t->block & 63)))
+        return b64i_fail(B64_BAD_ARG, "bad block");
+    if (t->units_per_lane && t->units_per_lane != 1 && t->units_per_lane != 2 && t->units_per_lane != 4 &&
+        t->units_per_lane != 8)
+        return b64i_fail(B64_BAD_ARG, "units_per_lane must be 1, 2, 4 or 8");
+    // grid: blocks per CU; -1 selects one workgroup per tile
+    if (t->grid && (t->grid < -1 || t->grid > 4096))
+        return b64i_fail(B64_BAD_ARG, "blocks per CU must be -1 or 1..4096");
     if (t->layout < 0 || t->layout > (dir == 0 ? 2 : 1))
         return b64i_fail(B64_BAD_ARG, "map must be 0 (LDS tables), 1 (register maps) or, for encode, 2 (pair table)");
+    if (t->block) g_single[dir].block = t->block;
+    if (t->units_per_lane) g_single[dir].upl = t->units_per_lane;
+    if (t->grid) g_single[dir].blocks_per_cu = t->grid < 0 ? 0 : t->grid;
     g_single[dir].map = t->layout;
     return B64_OK;
 }

@@ -626,11 +626,10 @@ namespace {
 // Smallest tile of any launch shape: sizes the workspace.
 constexpr int64_t WS_MIN_TILE = 256 * 16;
 
-struct WsShape {  // default: the fastest shape of a sweep on MI355X (MIME text, 1.47 GB)
-    std::atomic<int> block{256};
-    std::atomic<int> cpl{2};
-};
-WsShape g_ws;
+// Launch shape, block << 8 | chunks per lane, in one word so that a call
+// always reads a pair that was set together. Default: the fastest shape of a
+// sweep on MI355X (MIME text, 1.47 GB).
+std::atomic<int> g_ws{256 << 8 | 2};
 
 int64_t ws_tiles(int64_t n, int64_t tile) { return (n + tile - 1) / tile; }
 int64_t ws_words(int64_t T) { return WS_SLOT_WORDS + 2 * T + (T + WS_GROUP - 1) / WS_GROUP; }
@@ -660,7 +659,8 @@ int launch_ws(int block, int cpl, int64_t T, const uint8_t *src, int64_t n, uint
 int enqueue_ws(const uint8_t *src, int64_t n, uint8_t *dst, int alpha, int64_t *d_len, int64_t *d_err,
                unsigned long long *ws, hipStream_t s)
 {
-    const int block = g_ws.block.load(), cpl = g_ws.cpl.load();
+    const int shape = g_ws.load();
+    const int block = shape >> 8, cpl = shape & 0xff;
     const int64_t T = ws_tiles(n, (int64_t)block * 16 * cpl);
     const bool al = (((uintptr_t)src) & 3) == 0;
     int rc = al ? launch_ws<true>(block, cpl, T, src, n, dst, alpha, ws, s)
@@ -772,16 +772,16 @@ int64_t b64_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
 int b64_set_ws_tune(const b64_tune *t)
 {
     if (!t) return b64i_fail(B64_BAD_ARG, "null tune");
-    const int block = t->block ? t->block : g_ws.block.load();
-    const int cpl = t->units_per_lane ? t->units_per_lane : g_ws.cpl.load();
+    const int cur = g_ws.load();
+    const int block = t->block ? t->block : cur >> 8;
+    const int cpl = t->units_per_lane ? t->units_per_lane : cur & 0xff;
     const bool ok = (block == 256 && (cpl == 1 || cpl == 2 || cpl == 4 || cpl == 8)) ||
                     (block == 512 && (cpl == 1 || cpl == 2 || cpl == 4)) ||
                     (block == 1024 && (cpl == 1 || cpl == 2));
     if (!ok)
         return b64i_fail(B64_BAD_ARG, "whitespace-decode shape: block 256 (1/2/4/8 chunks), 512 (1/2/4) "
                                       "or 1024 (1/2) with 16-byte chunks per lane");
-    g_ws.block = block;
-    g_ws.cpl = cpl;
+    g_ws = block << 8 | cpl;
     return B64_OK;
 }
 

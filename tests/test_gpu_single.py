@@ -136,7 +136,8 @@ def test_injected_errors_and_minimum_offset():
 
 @pytest.mark.parametrize("soff,doff", [(1, 0), (0, 1), (2, 3), (3, 2), (5, 7), (13, 15), (4, 8)])
 def test_misaligned_subbuffers(soff, doff):
-    for n in [0, 1, 2, 3, 11, 12, 13, 100, 4097, 100_001]:
+    # 1,000,003 bytes: decode leaves the one-workgroup kernel (256 KiB and below)
+    for n in [0, 1, 2, 3, 11, 12, 13, 100, 4097, 100_001, 1_000_003]:
         x = rnd(n, n + soff)
         big = torch.zeros(n + 64, dtype=torch.uint8, device=DEV)
         big[soff:soff + n] = dev(x) if n else big[:0]

@@ -317,24 +317,69 @@ __device__ __forceinline__ void cursor_seek(Cursor &c, const BatchArgs &a, int64
     }
 }
 
-// Units gs + lane of one 64-unit group (gs < U); advances the cursor.
-__device__ __forceinline__ LaneRef resolve_group(Cursor &c, const BatchArgs &a, int64_t gs)
+// Units (g + k) * 64 + lane of the UPL groups g .. g + UPL - 1 (those below
+// g1), all resolved from one window of boundaries so that no group waits for
+// the one before it: the cursor's message m0 and the starts of the next 64
+// messages (one load), a 64-way shuffle search per lane, then every group's
+// metadata in one round of loads (none for lanes in the cursor's message).
+// Units more than 64 messages past m0 take the general search. The cursor
+// then moves once, to the message of the last unit resolved.
+template <int UPL>
+__device__ __forceinline__ void resolve_groups(Cursor &c, const BatchArgs &a, int64_t g, int64_t g1,
+                                               LaneRef (&r)[UPL])
 {
-    cursor_seek(c, a, gs);
-    const int64_t u = gs + __lane_id();
-    if (gs + 64 <= c.u1) {  // whole group inside the cursor's message
-        LaneRef r;
-        r.valid = true;
-        r.mm = c.m; r.j = u - c.u0; r.b = c.b; r.n = c.n; r.o = c.o; r.fl = c.fl;
-        return r;
+    cursor_seek(c, a, g * 64);
+    const int lane = __lane_id();
+    const int64_t m0 = c.m;
+    const int64_t idx = m0 + 1 + lane;
+    const int64_t B = idx <= a.N ? a.unit_off[idx] : INT64_MAX;  // first unit of message m0 + 1 + lane
+    const int64_t b63 = __shfl(B, 63, 64);
+    int64_t d[UPL];  // message of the unit, relative to m0
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const int64_t u = (g + k) * 64 + lane;
+        r[k].valid = g + k < g1 && u < a.U;
+        int cnt = 0;
+#pragma unroll
+        for (int stp = 32; stp >= 1; stp >>= 1) {
+            const int64_t b = __shfl(B, cnt + stp - 1, 64);
+            if (b <= u) cnt += stp;
+        }
+        if (cnt == 63 && b63 <= u) cnt = 64;
+        d[k] = cnt;
+        const bool far = r[k].valid && cnt == 64;
+        if (__ballot(far)) {  // rare: more than 64 messages ahead
+            const int64_t m2 = lane_find_msg(a.unit_off, a.N, m0 + 64, u, far);
+            if (far) d[k] = m2 - m0;
+        }
     }
-    const LaneRef r = lane_ref(a, c.m, u);
-    // the next group starts in the message of this group's last valid unit or later
-    const unsigned long long vb = __ballot(r.valid);
-    const int top = 63 - __clzll(vb);
-    const int64_t last = uniform64(__shfl(r.mm, top, 64));
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const int64_t u = (g + k) * 64 + lane;
+        const int64_t m = m0 + d[k];
+        const int64_t wu = __shfl(B, (int)min(max(d[k] - 1, (int64_t)0), (int64_t)63), 64);
+        r[k].mm = m;
+        r[k].j = 0; r[k].b = c.b; r[k].n = c.n; r[k].o = c.o; r[k].fl = c.fl;
+        if (r[k].valid) {
+            if (d[k] == 0) {
+                r[k].j = u - c.u0;
+            } else {
+                r[k].j = u - (d[k] <= 64 ? wu : a.unit_off[m]);
+                r[k].b = a.msgs.b(m);
+                r[k].n = a.msgs.n(m);
+                r[k].o = a.out_off[m];
+                r[k].fl = a.flags ? a.flags[m] : 0;
+            }
+        }
+    }
+    // the next iteration starts in the message of the last unit resolved here, or later
+    int64_t last = m0;
+#pragma unroll
+    for (int k = 0; k < UPL; k++) {
+        const unsigned long long vb = __ballot(r[k].valid);
+        if (vb) last = uniform64(__shfl(r[k].mm, 63 - __clzll(vb), 64));
+    }
     if (last != c.m) cursor_load(c, a, last);
-    return r;
 }
 
 // Contiguous share [g0, g1) of the 64-unit groups for the calling wave.
@@ -383,15 +428,11 @@ __global__ __launch_bounds__(1024) void k_enc_batch_w(
         LaneRef r[UPL];
         uint32_t w[UPL][3];
         bool full[UPL];
+        resolve_groups<UPL>(c, a, g, g1, r);
 #pragma unroll
         for (int k = 0; k < UPL; k++) {
-            r[k].valid = false;
-            full[k] = false;
-            if (g + k < g1) {
-                r[k] = resolve_group(c, a, (g + k) * 64);
-                full[k] = r[k].valid && 12 * r[k].j + 12 <= r[k].n;
-                if (full[k]) load12(src + r[k].b + 12 * r[k].j, w[k][0], w[k][1], w[k][2]);
-            }
+            full[k] = r[k].valid && 12 * r[k].j + 12 <= r[k].n;
+            if (full[k]) load12(src + r[k].b + 12 * r[k].j, w[k][0], w[k][1], w[k][2]);
         }
 #pragma unroll
         for (int k = 0; k < UPL; k++)
@@ -437,15 +478,11 @@ __global__ __launch_bounds__(1024) void k_dec_batch_w(
         LaneRef r[UPL];
         uint32_t w[UPL][4];
         bool interior[UPL];
+        resolve_groups<UPL>(c, a, g, g1, r);
 #pragma unroll
         for (int k = 0; k < UPL; k++) {
-            r[k].valid = false;
-            interior[k] = false;
-            if (g + k < g1) {
-                r[k] = resolve_group(c, a, (g + k) * 64);
-                interior[k] = r[k].valid && 16 * r[k].j + 16 < r[k].n;
-                if (interior[k]) load16(src + r[k].b + 16 * r[k].j, w[k][0], w[k][1], w[k][2], w[k][3]);
-            }
+            interior[k] = r[k].valid && 16 * r[k].j + 16 < r[k].n;
+            if (interior[k]) load16(src + r[k].b + 16 * r[k].j, w[k][0], w[k][1], w[k][2], w[k][3]);
         }
 #pragma unroll
         for (int k = 0; k < UPL; k++)

@@ -24,7 +24,7 @@ from . import codec
 SPACE = {
     0: ((256, 512, 1024), (1, 2, 4), (8, 16, 32)),
     # finer per-wave shares balance the uneven per-message costs better
-    1: ((64, 128, 256), (1, 2), (16, 32, 64, 128)),
+    1: ((64, 128, 256), (1, 2, 4), (16, 32, 64, 128)),
 }
 DEFAULT = {"block": 512, "units_per_lane": 2, "grid_per_cu": 32, "layout": 0}
 

@@ -407,36 +407,39 @@ __global__ __launch_bounds__(1024) void k_enc_batch_w(
     if (g0 >= g1) return;
     Cursor c;
     cursor_load(c, a, wave_find_msg(unit_off, N, g0 * 64));
-    for (int64_t g = g0; g < g1; g += UPL) {
-        // UPL whole groups of full units inside the cursor's message: the
-        // single-buffer step (no per-lane message lookup or tail branches)
-        if (g + UPL <= g1) {
-            const int64_t gs = g * 64;
-            cursor_seek(c, a, gs);
-            if (gs + 64 * UPL <= c.u0 + c.n / 12) {
-                const uint8_t *p = src + c.b;
-                uint8_t *q = dst + c.o;
-                const MapCtx mc{(const uint8_t *)s_tab + 64 * (c.fl & M_URL)};
-                const int64_t first = gs - c.u0 + __lane_id();
-                if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0)
-                    enc_step<true, UPL, false>(p, q, first, 64, 0, mc);
-                else
-                    enc_step<false, UPL, false>(p, q, first, 64, 0, mc);
-                continue;
+    for (int64_t g = g0; g < g1;) {
+        // whole groups of full units inside the cursor's message: the
+        // single-buffer step (no per-lane message lookup or tail branches),
+        // UPL groups at a time while they fit, then one at a time
+        const int64_t gs = g * 64;
+        cursor_seek(c, a, gs);
+        const int64_t inside = (c.u0 + c.n / 12 - gs) / 64;
+        if (inside >= 1) {
+            const uint8_t *p = src + c.b;
+            uint8_t *q = dst + c.o;
+            const MapCtx mc{(const uint8_t *)s_tab + 64 * (c.fl & M_URL)};
+            const int64_t first = gs - c.u0 + __lane_id();
+            const bool al = (((uintptr_t)p | (uintptr_t)q) & 3) == 0;
+            if (inside >= UPL && g + UPL <= g1) {
+                if (al) enc_step<true, UPL, false>(p, q, first, 64, 0, mc);
+                else enc_step<false, UPL, false>(p, q, first, 64, 0, mc);
+                g += UPL;
+            } else {
+                if (al) enc_step<true, 1, false>(p, q, first, 64, 0, mc);
+                else enc_step<false, 1, false>(p, q, first, 64, 0, mc);
+                g += 1;
             }
+            continue;
         }
-        LaneRef r[UPL];
-        uint32_t w[UPL][3];
-        bool full[UPL];
-        resolve_groups<UPL>(c, a, g, g1, r);
-#pragma unroll
-        for (int k = 0; k < UPL; k++) {
-            full[k] = r[k].valid && 12 * r[k].j + 12 <= r[k].n;
-            if (full[k]) load12(src + r[k].b + 12 * r[k].j, w[k][0], w[k][1], w[k][2]);
-        }
-#pragma unroll
-        for (int k = 0; k < UPL; k++)
-            if (r[k].valid) enc_batch_unit(src, dst, r[k], full[k], w[k], (const uint8_t *)s_tab);
+        // one group holding a message boundary or a message's final unit,
+        // resolved per lane; the single-buffer step resumes after it
+        LaneRef r[1];
+        uint32_t w[3];
+        resolve_groups<1>(c, a, g, g1, r);
+        const bool full = r[0].valid && 12 * r[0].j + 12 <= r[0].n;
+        if (full) load12(src + r[0].b + 12 * r[0].j, w[0], w[1], w[2]);
+        if (r[0].valid) enc_batch_unit(src, dst, r[0], full, w, (const uint8_t *)s_tab);
+        g += 1;
     }
 }
 
@@ -456,38 +459,40 @@ __global__ __launch_bounds__(1024) void k_dec_batch_w(
     if (g0 >= g1) return;
     Cursor c;
     cursor_load(c, a, wave_find_msg(unit_off, N, g0 * 64));
-    for (int64_t g = g0; g < g1; g += UPL) {
-        // UPL whole groups of interior units inside the cursor's message: the
-        // single-buffer step
-        if (g + UPL <= g1) {
-            const int64_t gs = g * 64;
-            cursor_seek(c, a, gs);
-            if (gs + 64 * UPL <= c.u0 + (c.n - 1) / 16) {
-                const uint8_t *p = src + c.b;
-                uint8_t *q = dst + c.o;
-                const MapCtx mc{(const uint8_t *)s_tab + 256 * (c.fl & M_URL)};
-                unsigned long long *slot = (unsigned long long *)&err_off[c.m];
-                const int64_t first = gs - c.u0 + __lane_id();
-                if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0)
-                    dec_step<true, UPL, false>(p, q, first, 64, 0, mc, slot);
-                else
-                    dec_step<false, UPL, false>(p, q, first, 64, 0, mc, slot);
-                continue;
+    for (int64_t g = g0; g < g1;) {
+        // whole groups of interior units inside the cursor's message: the
+        // single-buffer step, UPL groups at a time while they fit, then one
+        // at a time
+        const int64_t gs = g * 64;
+        cursor_seek(c, a, gs);
+        const int64_t inside = (c.u0 + (c.n - 1) / 16 - gs) / 64;
+        if (inside >= 1) {
+            const uint8_t *p = src + c.b;
+            uint8_t *q = dst + c.o;
+            const MapCtx mc{(const uint8_t *)s_tab + 256 * (c.fl & M_URL)};
+            unsigned long long *slot = (unsigned long long *)&err_off[c.m];
+            const int64_t first = gs - c.u0 + __lane_id();
+            const bool al = (((uintptr_t)p | (uintptr_t)q) & 3) == 0;
+            if (inside >= UPL && g + UPL <= g1) {
+                if (al) dec_step<true, UPL, false>(p, q, first, 64, 0, mc, slot);
+                else dec_step<false, UPL, false>(p, q, first, 64, 0, mc, slot);
+                g += UPL;
+            } else {
+                if (al) dec_step<true, 1, false>(p, q, first, 64, 0, mc, slot);
+                else dec_step<false, 1, false>(p, q, first, 64, 0, mc, slot);
+                g += 1;
             }
+            continue;
         }
-        LaneRef r[UPL];
-        uint32_t w[UPL][4];
-        bool interior[UPL];
-        resolve_groups<UPL>(c, a, g, g1, r);
-#pragma unroll
-        for (int k = 0; k < UPL; k++) {
-            interior[k] = r[k].valid && 16 * r[k].j + 16 < r[k].n;
-            if (interior[k]) load16(src + r[k].b + 16 * r[k].j, w[k][0], w[k][1], w[k][2], w[k][3]);
-        }
-#pragma unroll
-        for (int k = 0; k < UPL; k++)
-            if (r[k].valid)
-                dec_batch_unit(src, dst, r[k], interior[k], w[k], (const uint8_t *)s_tab, out_len, err_off);
+        // one group holding a message boundary or a message's final unit,
+        // resolved per lane; the single-buffer step resumes after it
+        LaneRef r[1];
+        uint32_t w[4];
+        resolve_groups<1>(c, a, g, g1, r);
+        const bool interior = r[0].valid && 16 * r[0].j + 16 < r[0].n;
+        if (interior) load16(src + r[0].b + 16 * r[0].j, w[0], w[1], w[2], w[3]);
+        if (r[0].valid) dec_batch_unit(src, dst, r[0], interior, w, (const uint8_t *)s_tab, out_len, err_off);
+        g += 1;
     }
 }
 

@@ -317,69 +317,66 @@ __device__ __forceinline__ void cursor_seek(Cursor &c, const BatchArgs &a, int64
     }
 }
 
-// Units (g + k) * 64 + lane of the UPL groups g .. g + UPL - 1 (those below
-// g1), all resolved from one window of boundaries so that no group waits for
-// the one before it: the cursor's message m0 and the starts of the next 64
-// messages (one load), a 64-way shuffle search per lane, then every group's
-// metadata in one round of loads (none for lanes in the cursor's message).
-// Units more than 64 messages past m0 take the general search. The cursor
-// then moves once, to the message of the last unit resolved.
-template <int UPL>
-__device__ __forceinline__ void resolve_groups(Cursor &c, const BatchArgs &a, int64_t g, int64_t g1,
-                                               LaneRef (&r)[UPL])
+// Units gs + lane of one 64-unit group (gs < U) that holds a message boundary
+// or a message's final unit. One load brings the starts of the 64 messages
+// after the cursor's message m0; each lane finds its message with a 64-way
+// shuffle search and loads that message's metadata (none in the cursor's
+// message; units more than 64 messages past m0 take the general search). The
+// cursor then moves to the message of the group's last unit, from the
+// registers of the lane that holds it.
+__device__ __forceinline__ LaneRef resolve_group(Cursor &c, const BatchArgs &a, int64_t gs)
 {
-    cursor_seek(c, a, g * 64);
+    cursor_seek(c, a, gs);
     const int lane = __lane_id();
     const int64_t m0 = c.m;
     const int64_t idx = m0 + 1 + lane;
     const int64_t B = idx <= a.N ? a.unit_off[idx] : INT64_MAX;  // first unit of message m0 + 1 + lane
     const int64_t b63 = __shfl(B, 63, 64);
-    int64_t d[UPL];  // message of the unit, relative to m0
+    const int64_t u = gs + lane;
+    LaneRef r;
+    r.valid = u < a.U;
+    int cnt = 0;
 #pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const int64_t u = (g + k) * 64 + lane;
-        r[k].valid = g + k < g1 && u < a.U;
-        int cnt = 0;
-#pragma unroll
-        for (int stp = 32; stp >= 1; stp >>= 1) {
-            const int64_t b = __shfl(B, cnt + stp - 1, 64);
-            if (b <= u) cnt += stp;
-        }
-        if (cnt == 63 && b63 <= u) cnt = 64;
-        d[k] = cnt;
-        const bool far = r[k].valid && cnt == 64;
-        if (__ballot(far)) {  // rare: more than 64 messages ahead
-            const int64_t m2 = lane_find_msg(a.unit_off, a.N, m0 + 64, u, far);
-            if (far) d[k] = m2 - m0;
-        }
+    for (int stp = 32; stp >= 1; stp >>= 1) {
+        const int64_t b = __shfl(B, cnt + stp - 1, 64);
+        if (b <= u) cnt += stp;
     }
-#pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const int64_t u = (g + k) * 64 + lane;
-        const int64_t m = m0 + d[k];
-        const int64_t wu = __shfl(B, (int)min(max(d[k] - 1, (int64_t)0), (int64_t)63), 64);
-        r[k].mm = m;
-        r[k].j = 0; r[k].b = c.b; r[k].n = c.n; r[k].o = c.o; r[k].fl = c.fl;
-        if (r[k].valid) {
-            if (d[k] == 0) {
-                r[k].j = u - c.u0;
-            } else {
-                r[k].j = u - (d[k] <= 64 ? wu : a.unit_off[m]);
-                r[k].b = a.msgs.b(m);
-                r[k].n = a.msgs.n(m);
-                r[k].o = a.out_off[m];
-                r[k].fl = a.flags ? a.flags[m] : 0;
-            }
-        }
+    if (cnt == 63 && b63 <= u) cnt = 64;
+    int64_t d = cnt;  // message of unit u, relative to m0
+    const bool far = r.valid && cnt == 64;
+    if (__ballot(far)) {  // rare: more than 64 messages ahead
+        const int64_t m2 = lane_find_msg(a.unit_off, a.N, m0 + 64, u, far);
+        if (far) d = m2 - m0;
     }
-    // the next iteration starts in the message of the last unit resolved here, or later
-    int64_t last = m0;
-#pragma unroll
-    for (int k = 0; k < UPL; k++) {
-        const unsigned long long vb = __ballot(r[k].valid);
-        if (vb) last = uniform64(__shfl(r[k].mm, 63 - __clzll(vb), 64));
+    const int64_t m = m0 + d;
+    const int64_t wu = __shfl(B, (int)min(max(d - 1, (int64_t)0), (int64_t)63), 64);  // start of m when 1 <= d <= 64
+    const int64_t wn = __shfl(B, (int)min(d, (int64_t)63), 64);                     // start of m + 1 when d <= 63
+    int64_t u0 = c.u0, u1 = c.u1;
+    r.mm = m;
+    r.b = c.b; r.n = c.n; r.o = c.o; r.fl = c.fl;
+    if (r.valid && d > 0) {
+        u0 = d <= 64 ? wu : a.unit_off[m];
+        u1 = d <= 63 ? wn : a.unit_off[m + 1];
+        r.b = a.msgs.b(m);
+        r.n = a.msgs.n(m);
+        r.o = a.out_off[m];
+        r.fl = a.flags ? a.flags[m] : 0;
     }
-    if (last != c.m) cursor_load(c, a, last);
+    r.j = u - u0;
+    // the next group starts in the message of this group's last valid unit or later
+    const unsigned long long vb = __ballot(r.valid);
+    const int top = 63 - __clzll(vb);
+    const int64_t last = uniform64(__shfl(r.mm, top, 64));
+    if (last != c.m) {
+        c.m = last;
+        c.u0 = uniform64(__shfl(u0, top, 64));
+        c.u1 = uniform64(__shfl(u1, top, 64));
+        c.b = uniform64(__shfl(r.b, top, 64));
+        c.n = uniform64(__shfl(r.n, top, 64));
+        c.o = uniform64(__shfl(r.o, top, 64));
+        c.fl = __builtin_amdgcn_readfirstlane(__shfl(r.fl, top, 64));
+    }
+    return r;
 }
 
 // Contiguous share [g0, g1) of the 64-unit groups for the calling wave.
@@ -433,12 +430,11 @@ __global__ __launch_bounds__(1024) void k_enc_batch_w(
         }
         // one group holding a message boundary or a message's final unit,
         // resolved per lane; the single-buffer step resumes after it
-        LaneRef r[1];
+        const LaneRef r = resolve_group(c, a, gs);
         uint32_t w[3];
-        resolve_groups<1>(c, a, g, g1, r);
-        const bool full = r[0].valid && 12 * r[0].j + 12 <= r[0].n;
-        if (full) load12(src + r[0].b + 12 * r[0].j, w[0], w[1], w[2]);
-        if (r[0].valid) enc_batch_unit(src, dst, r[0], full, w, (const uint8_t *)s_tab);
+        const bool full = r.valid && 12 * r.j + 12 <= r.n;
+        if (full) load12(src + r.b + 12 * r.j, w[0], w[1], w[2]);
+        if (r.valid) enc_batch_unit(src, dst, r, full, w, (const uint8_t *)s_tab);
         g += 1;
     }
 }
@@ -486,12 +482,11 @@ __global__ __launch_bounds__(1024) void k_dec_batch_w(
         }
         // one group holding a message boundary or a message's final unit,
         // resolved per lane; the single-buffer step resumes after it
-        LaneRef r[1];
+        const LaneRef r = resolve_group(c, a, gs);
         uint32_t w[4];
-        resolve_groups<1>(c, a, g, g1, r);
-        const bool interior = r[0].valid && 16 * r[0].j + 16 < r[0].n;
-        if (interior) load16(src + r[0].b + 16 * r[0].j, w[0], w[1], w[2], w[3]);
-        if (r[0].valid) dec_batch_unit(src, dst, r[0], interior, w, (const uint8_t *)s_tab, out_len, err_off);
+        const bool interior = r.valid && 16 * r.j + 16 < r.n;
+        if (interior) load16(src + r.b + 16 * r.j, w[0], w[1], w[2], w[3]);
+        if (r.valid) dec_batch_unit(src, dst, r, interior, w, (const uint8_t *)s_tab, out_len, err_off);
         g += 1;
     }
 }

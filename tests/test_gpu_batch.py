@@ -335,3 +335,24 @@ def test_batch_misaligned_user_output_slots(layout):
             # the gap after the slot's capacity is untouched
             assert (got[out_off[i] + size[i]:out_off[i + 1]] == 0xAB).all(), (direction, i)
         assert host(base)[0] == 0xAB
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_groups_spanning_more_than_64_messages(layout):
+    """Runs of empty messages between short ones, so that one 64-unit group
+    spans hundreds of messages: the per-lane search must go past its first
+    window of 64 message starts. Short messages of both alphabets, and a long
+    one after the runs so the single-buffer step resumes."""
+    rng = np.random.default_rng(50 + layout)
+    lens = []
+    for _ in range(1500):
+        lens += [0] * int(rng.integers(0, 200))
+        lens.append(int(rng.integers(1, 40)))
+    lens.append(200_000)
+    lens += [0] * 300 + [5]
+    flags = rng.integers(0, 2, len(lens)).astype(np.uint8)
+    data, off = packed(lens, 60 + layout)
+    for tune in (dict(layout=layout), dict(layout=layout, block=256, units_per_lane=4)):
+        check_encode(data, off, flags, tune=tune)
+        text, toff = encode_text(data, off, flags)
+        check_decode(text, toff, flags, tune=tune)

@@ -31,6 +31,14 @@ MUTANTS = {
     "offset_off_by_one": ("if (!oracle_char_ok(c, n, i, inv)) return i;",
                           "if (!oracle_char_ok(c, n, i, inv)) return i + 1;"),
     "dec_no_early_stop": ("        if (c[i + 2] == '=') return o;\n", ""),
+    # whitespace-tolerant decode (Appendix B)
+    "ws_also_tab": ("if (v == ' ' || v == '\\n' || v == '\\r') continue;",
+                    "if (v == ' ' || v == '\\n' || v == '\\r' || v == '\\t') continue;"),
+    "ws_no_cr": ("if (v == ' ' || v == '\\n' || v == '\\r') continue;", "if (v == ' ' || v == '\\n') continue;"),
+    "ws_stripped_offsets": ("if (len < 0) *err_off = (*err_off >= m) ? n : pos[*err_off];",
+                            "if (len < 0) *err_off = (*err_off >= m) ? n : *err_off;"),
+    "ws_length_error_at_m": ("if (len < 0) *err_off = (*err_off >= m) ? n : pos[*err_off];",
+                             "if (len < 0) *err_off = (*err_off >= m) ? m : pos[*err_off];"),
 }
 
 PIN_TESTS = [
@@ -46,6 +54,8 @@ PIN_TESTS = [
     lambda t1: pins.test_rejection_sweep_all_256_bytes(t1, oracle.URL),
     lambda t1: pins.test_all_one_and_two_byte_tails(t1, oracle.URL),
     lambda t1: pins.test_single_injected_offset_is_exact(),
+    lambda t1: pins.test_whitespace_strip_and_decode(),
+    lambda t1: pins.test_whitespace_mode_classifies_every_byte_value(),
 ]
 
 

@@ -474,6 +474,9 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
         for (int j = 0; j < 4; j++)
             if (keep & (0x80u << (8 * j))) s_txt[pos++] = (uint8_t)(x >> (8 * j));
     }
+    // 16 bytes of a symbol ('A', value 0) after the last kept byte: the unit
+    // that reaches past the stripped text looks up no marks there
+    if (tid < 16) s_txt[F + ktot + tid] = (uint8_t)'A';
     __syncthreads();
 
     // 4. decode the quads that end in this tile: stripped bytes
@@ -503,19 +506,20 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
         const uint4 c = s_txt4[(F - r0 + 4 * s0) >> 4];
         uint32_t vs[4] = {c.x, c.y, c.z, c.w};
         if (hd) {
+            // the head's quads; its other dwords hold a symbol, so they raise
+            // no marks
+            const uint32_t sym = 0x41414141u;
             if (hq == 1) {
-                vs[0] = c.w;
+                vs[0] = c.w; vs[1] = sym; vs[2] = sym;
             } else if (hq == 2) {
-                vs[0] = c.z;
-                vs[1] = c.w;
+                vs[0] = c.z; vs[1] = c.w; vs[2] = sym;
             } else {
-                vs[0] = c.y;
-                vs[1] = c.z;
-                vs[2] = c.w;
+                vs[0] = c.y; vs[1] = c.z; vs[2] = c.w;
             }
+            vs[3] = sym;
         }
         uint8_t *q = q0 + 3 * (int64_t)s0;
-        if (nq == 4) {
+        {
             uint32_t tq[4], mk = 0;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
@@ -525,15 +529,20 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
                 tq[i] = (a << 18) | (b << 12) | (c << 6) | e;
             }
             if (!(mk & 0x80u)) {
-                const uint32_t o[3] = {perm(tq[1], tq[0], 0x06000102u), perm(tq[2], tq[1], 0x05060001u),
-                                       perm(tq[3], tq[2], 0x04050600u)};
-                store_words<3, true>(q, o);
+                const uint32_t o[4] = {perm(tq[1], tq[0], 0x06000102u), perm(tq[2], tq[1], 0x05060001u),
+                                       perm(tq[3], tq[2], 0x04050600u), 0u};
+                if (nq == 4) {
+                    const uint32_t o3[3] = {o[0], o[1], o[2]};
+                    store_words<3, true>(q, o3);
+                } else if (nq > 0) {
+                    store_upto16(q, o, 3 * nq);  // the head unit, or the text's last quads here
+                }
                 continue;
             }
         }
-        // a partial unit, or marks: '=' counts as 0 and the bytes it pads are
-        // not written (any other placement is an error, and the output of an
-        // invalid input is unspecified)
+        // marks (rare): '=' counts as 0 and the bytes it pads are not written
+        // (any other placement is an error, and the output of an invalid input
+        // is unspecified)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             if (4 * i < nb) {

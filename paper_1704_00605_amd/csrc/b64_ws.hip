@@ -385,7 +385,6 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     __shared__ uint4 s_txt4[(32 + TILE + 32) / 16];
     uint8_t *const s_txt = (uint8_t *)s_txt4;
     __shared__ uint32_t s_seg[E];          // kept bytes per segment
-    __shared__ uint32_t s_pre[E];          // their exclusive prefix
 
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
     lds_fill(s_tab, c_ws.cls[alpha], 256);
@@ -445,25 +444,28 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     }
     __syncthreads();
     // 2. exclusive prefix over the (k2, wave) segments, computed by every
-    // wave for its own segments (no barrier), and the tile's kept total
-    uint32_t segpre[K2];
-    uint32_t ktot;
+    // wave (no barrier), and the tile's kept total: lane i holds segment i
+    // (segments 2i and 2i + 1 when there are more than 64), scanned with DPP;
+    // a segment's prefix is read out with readlane (here for the wave's own
+    // segments, later by the rare rescan for any segment)
+    constexpr int SPL = E > 64 ? 2 : 1;  // segments per lane
+    uint32_t sa, sx, ktot;               // lane's first segment count, its exclusive prefix
     {
-        const uint32_t a0 = 2 * lane < E ? s_seg[2 * lane] : 0u;
-        const uint32_t a1 = 2 * lane + 1 < E ? s_seg[2 * lane + 1] : 0u;
-        const uint32_t pair = a0 + a1;
-        const uint32_t inc = wave_incl_sum(pair);
-        const uint32_t ex = inc - pair;  // prefix of segment 2 * lane
+        const uint32_t a0 = SPL * lane < E ? s_seg[SPL * lane] : 0u;
+        const uint32_t a1 = (SPL == 2 && 2 * lane + 1 < E) ? s_seg[2 * lane + 1] : 0u;
+        const uint32_t sum = a0 + a1;
+        const uint32_t inc = wave_incl_sum(sum);
+        sx = inc - sum;
+        sa = a0;
         ktot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-#pragma unroll
-        for (int k = 0; k < K2; k++) {
-            const int e = k * NW + wid;
-            const uint32_t ex2 = (uint32_t)__builtin_amdgcn_readlane((int)ex, e >> 1);
-            const uint32_t a02 = (uint32_t)__builtin_amdgcn_readlane((int)a0, e >> 1);
-            segpre[k] = (e & 1) ? ex2 + a02 : ex2;
-            if (lane == 0) s_pre[e] = segpre[k];
-        }
     }
+    auto seg_prefix = [&](int e) -> uint32_t {  // e: wave-uniform segment index
+        const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)sx, SPL == 1 ? e : e >> 1);
+        return (SPL == 2 && (e & 1)) ? x + (uint32_t)__builtin_amdgcn_readlane((int)sa, e >> 1) : x;
+    };
+    uint32_t segpre[K2];
+#pragma unroll
+    for (int k = 0; k < K2; k++) segpre[k] = seg_prefix(k * NW + wid);
 
     // 3. compaction: kept raw bytes to s_txt[F + tile-stripped index]
 #pragma unroll
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
             const uint32_t x = s_raw[dw];
             const uint32_t keep = kept8(x);
             const uint32_t c = __popc(keep);
-            const int64_t at = P + s_pre[e] + (wave_incl_sum(c) - c);
+            const int64_t at = P + seg_prefix(e) + (wave_incl_sum(c) - c);
             const int64_t off = base + 4 * (int64_t)dw;
             unsigned long long eb = ERR_NONE, eo = ERR_NONE, es = ERR_NONE;
             uint32_t rank = 0;

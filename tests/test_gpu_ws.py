@@ -217,7 +217,7 @@ def test_ws_every_control_byte_is_an_error():
                 assert check(c)[:2] == (-1, j), (shape, b, j)
 
 
-@pytest.mark.parametrize("shape", [(256, 1), (512, 2)])
+@pytest.mark.parametrize("shape", [(256, 1), (512, 2), (256, 8)])
 def test_ws_marks_next_to_tile_boundaries(shape):
     """Invalid bytes and '=' just before and after tile boundaries, where the
     last kept bytes of a tile form a partial quad that the next tile decodes."""

@@ -198,7 +198,8 @@ __global__ __launch_bounds__(BLOCK) void k_ws_count(const uint8_t *__restrict__ 
     constexpr int NW = BLOCK / 64;
     constexpr int E = CPL * NW;
     __shared__ uint32_t s_cnt[E], s_car[E];
-    const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+    const int tid = threadIdx.x, lane = __lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     const int64_t t = blockIdx.x;
     if (t == 0 && tid == 0) {
         ws[1] = ERR_NONE;
@@ -386,7 +387,8 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     uint8_t *const s_txt = (uint8_t *)s_txt4;
     __shared__ uint32_t s_seg[E];          // kept bytes per segment
 
-    const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+    const int tid = threadIdx.x, lane = __lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     lds_fill(s_tab, c_ws.cls[alpha], 256);
     const uint8_t *tab = (const uint8_t *)s_tab;
     const int64_t t = blockIdx.x;

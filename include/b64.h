@@ -331,8 +331,9 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
 int b64_set_single_tune(int dir, const b64_tune *t);
 
 /* Launch shape of the whitespace-tolerant decode (tuning): block 256, 512 or
- * 1024 threads; units_per_lane = input dwords per lane per tile (2, 4 or 8);
- * other fields ignored; zero fields keep the current value. Process-wide. */
+ * 1024 threads; units_per_lane = 16-byte input chunks per lane per tile
+ * (256: 1, 2, 4 or 8; 512: 1, 2 or 4; 1024: 1 or 2); other fields ignored;
+ * zero fields keep the current value. Process-wide. */
 int b64_set_ws_tune(const b64_tune *t);
 
 /* Thread-local description of the last failure (never NULL). */

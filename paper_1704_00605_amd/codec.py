@@ -157,8 +157,11 @@ def decode_ws_async(src, out, result, workspace, alphabet=ALPHABET_STD, stream=N
     check(r, "b64_decode_ws_async")
 
 
-def set_ws_tune(block=0, dwords_per_lane=0):
-    t = Tune(block=block, units_per_lane=dwords_per_lane, grid=0, layout=0)
+def set_ws_tune(block=0, chunks_per_lane=0):
+    """Launch shape of the whitespace-tolerant decode (see b64_set_ws_tune):
+    block threads and 16-byte input chunks per lane per tile; zero keeps the
+    current value."""
+    t = Tune(block=block, units_per_lane=chunks_per_lane, grid=0, layout=0)
     check(lib().b64_set_ws_tune(ctypes.byref(t)), "b64_set_ws_tune")
 
 

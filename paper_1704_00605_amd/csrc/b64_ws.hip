@@ -1,6 +1,6 @@
 // gfx950 whitespace-tolerant decode (Appendix B: space, line feed and
 // carriage return are removed before decoding), and its C-ABI
-// (include/b64.h). The input is cut into tiles of blockDim * 4 * CPL bytes.
+// (include/b64.h). The input is cut into tiles of blockDim * 16 * CPL bytes.
 //
 //   k_ws_count    per tile: number of kept (non-whitespace) bytes and the
 //                 last three of them, from SWAR whitespace tests, and a flag

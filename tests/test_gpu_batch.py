@@ -264,6 +264,58 @@ def test_config4_shaped_heavy_mix_scaled():
     check_decode(text, toff, flags)
 
 
+def test_config4_full_size_sampled():
+    """The heavy-tailed mix at full size (8,192 messages, 7.25 GB, per-message
+    alphabets, 41 corrupted) in the autotuned launch shape, as timed: every
+    length and verdict against its closed form or the oracle, the corrupted
+    messages and a seeded sample of the others (the largest, the smallest,
+    the first and the last among them) byte for byte against the oracle one
+    by one, and every valid message's decoded bytes against its payload."""
+    from paper_1704_00605_amd import autotune
+
+    w = workloads.heavy_mix()
+    data, off, flags = w["payload"], w["in_off"], w["flags"]
+    N = off.size - 1
+    lens = np.diff(off)
+    src, in_off, fl = dev(data), dev(off), dev(flags)
+    tune_e, _ = autotune.tune(E, src, in_off, fl, in_off_host=off, reps=1, use_cache=False)
+    text, toff_d, tl = codec.encode_batch(src, in_off, flags=fl, tune=tune_e)
+    toff = host(toff_d)
+    assert np.array_equal(host(tl)[:N], 4 * ((lens + 2) // 3))
+    # corruptions as the benchmark applies them, on the device
+    ids, u, rk = w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"]
+    tlen = np.diff(toff)
+    pos = np.minimum(np.floor(u * tlen[ids]).astype(np.int64), np.maximum(tlen[ids] - 1, 0))
+    vals = np.array([workloads.corruption_byte(int(r), int(flags[i]), int(p), int(tlen[i]))
+                     for r, i, p in zip(rk, ids, pos)], np.uint8)
+    # the sample: corrupted messages plus seeded others, before the text changes
+    rng = np.random.default_rng(11)
+    clean = np.setdiff1d(np.arange(N), ids)
+    pick = np.unique(np.concatenate([ids, rng.choice(clean, 40, replace=False),
+                                     [clean[np.argmax(lens[clean])], clean[np.argmin(lens[clean])], clean[0], clean[-1]]]))
+    want_t, want_toff, _ = oracle.encode_batch(np.concatenate([data[off[i]:off[i + 1]] for i in pick]),
+                                               np.concatenate([[0], np.cumsum(lens[pick])]), flags[pick])
+    for k, i in enumerate(pick):
+        got = host(text[toff[i]:toff[i] + tlen[i]])
+        assert np.array_equal(got, want_t[want_toff[k]:want_toff[k + 1]]), i
+    text[dev(toff[ids] + pos)] = dev(vals)
+    tune_d, _ = autotune.tune(D, text, toff_d, fl, in_off_host=toff, reps=1, use_cache=False)
+    out, oo_d, ol, er = codec.decode_batch(text, toff_d, flags=fl, tune=tune_d)
+    oo, gl, ge = host(oo_d), host(ol)[:N], host(er)[:N]
+    bad = np.zeros(N, bool)
+    bad[ids] = True
+    assert np.array_equal(gl[~bad], lens[~bad]) and (ge[~bad] == -1).all()
+    sub = np.concatenate([host(text[toff[i]:toff[i + 1]]) for i in pick])
+    wd, wdo, wl, we = oracle.decode_batch(sub, np.concatenate([[0], np.cumsum(tlen[pick])]), flags[pick])
+    assert np.array_equal(gl[pick], wl) and np.array_equal(ge[pick], we)
+    for k, i in enumerate(pick):
+        if wl[k] > 0:
+            assert np.array_equal(host(out[oo[i]:oo[i] + wl[k]]), wd[wdo[k]:wdo[k] + wl[k]]), i
+    assert (we[np.isin(pick, ids)] >= 0).all()
+    for i in np.nonzero(~bad)[0]:
+        assert torch.equal(out[oo[i]:oo[i] + lens[i]], src[off[i]:off[i + 1]]), i
+
+
 def test_out_offsets_scan_sizes():
     rng = np.random.default_rng(7)
     for N in [0, 1, 2, 1023, 1024, 1025, 5000, 100_000]:

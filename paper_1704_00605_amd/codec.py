@@ -15,7 +15,9 @@ from ._lib import (ALPHABET_STD, ALPHABET_URL, DIR_DECODE, DIR_ENCODE, FLAG_NOPA
 
 __all__ = [
     "encode", "decode", "decode_async", "encoded_len", "decoded_max", "batch_out_offsets",
-    "encode_batch", "decode_batch", "encode_batch_gather", "decode_batch_gather", "encode_each", "decode_each", "workspace_bytes", "set_single_tune",
+    "encode_batch", "decode_batch", "encode_batch_gather", "decode_batch_gather", "encode_each", "decode_each",
+    "workspace_bytes", "Workspace", "set_single_tune", "decode_ws", "decode_ws_async", "ws_workspace_bytes",
+    "set_ws_tune",
     "ALPHABET_STD", "ALPHABET_URL", "MODE_STRICT", "MODE_NOPAD", "FLAG_URL", "FLAG_STRICT",
     "FLAG_NOPAD", "DIR_ENCODE", "DIR_DECODE", "Tune", "B64Error",
 ]
@@ -103,8 +105,7 @@ def decode_async(src, out, result, alphabet=ALPHABET_STD, stream=None):
     _dev_u8(out, "out")
     if out.numel() < decoded_max(src.numel(), alphabet & ~0xff):
         raise ValueError("out is too small")
-    if result.dtype != torch.int64 or result.numel() < 2 or not result.is_cuda:
-        raise TypeError("result must be an int64 CUDA tensor with 2 slots")
+    _result_slots(result)
     rp = result.data_ptr()
     r = lib().b64_decode_async(_ptr(src), src.numel(), _ptr(out), int(alphabet),
                                ctypes.c_void_p(rp), ctypes.c_void_p(rp + 8), _stream(stream))
@@ -148,8 +149,7 @@ def decode_ws_async(src, out, result, workspace, alphabet=ALPHABET_STD, stream=N
         raise ValueError("out is too small")
     if workspace.numel() < ws_workspace_bytes(n):
         raise ValueError("workspace is too small")
-    if result.dtype != torch.int64 or result.numel() < 2 or not result.is_cuda:
-        raise TypeError("result must be an int64 CUDA tensor with 2 slots")
+    _result_slots(result)
     rp = result.data_ptr()
     r = lib().b64_decode_ws_async(_ptr(src), n, _ptr(out), int(alphabet), ctypes.c_void_p(rp),
                                   ctypes.c_void_p(rp + 8), _ptr(workspace), workspace.numel(),
@@ -181,6 +181,33 @@ def _i64_dev(t, name):
     return t
 
 
+def _i64_slots(t, n, name):
+    """A caller's int64 device array that the kernels index up to n - 1."""
+    _i64_dev(t, name)
+    if t.numel() < n:
+        raise ValueError(f"{name} needs at least {n} entries")
+    return t
+
+
+def _flags_dev(flags, N):
+    """Per-message flags: None (standard alphabet, padded) or one uint8 per
+    message on the device."""
+    if flags is None:
+        return None
+    if not isinstance(flags, torch.Tensor) or flags.dtype != torch.uint8 or not flags.is_cuda \
+            or not flags.is_contiguous():
+        raise TypeError("flags must be a contiguous uint8 CUDA tensor")
+    if flags.numel() < N:
+        raise ValueError(f"flags needs one byte per message ({N})")
+    return flags
+
+
+def _result_slots(result):
+    if not isinstance(result, torch.Tensor) or result.dtype != torch.int64 or result.numel() < 2 \
+            or not result.is_cuda or not result.is_contiguous():
+        raise TypeError("result must be a contiguous int64 CUDA tensor with 2 slots")
+
+
 def workspace_bytes(N):
     return check(lib().b64_batch_workspace_bytes(int(N)), "workspace_bytes")
 
@@ -189,6 +216,7 @@ def batch_out_offsets(direction, in_off, flags=None, stream=None):
     """Device exclusive scan of the per-message output sizes (N+1 int64)."""
     in_off = _i64_dev(in_off, "in_off")
     N = in_off.numel() - 1
+    flags = _flags_dev(flags, N)
     out_off = torch.empty(N + 1, dtype=torch.int64, device=in_off.device)
     r = lib().b64_batch_out_offsets(int(direction), _ptr(in_off), N, _ptr(out_off),
                                     _ptr(flags), _stream(stream))
@@ -198,7 +226,9 @@ def batch_out_offsets(direction, in_off, flags=None, stream=None):
 
 class Workspace:
     """A reusable device workspace for the batched calls (grows on demand,
-    outside the launch path)."""
+    outside the launch path). Calls that pass no workspace share one default
+    per device, which suits calls on one stream; calls that may run at the
+    same time on different streams need a Workspace each."""
 
     def __init__(self, device=None):
         self.buf = None
@@ -230,13 +260,18 @@ def encode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
     in_off = _i64_dev(in_off, "in_off")
     N = in_off.numel() - 1
     dev = src.device
+    flags = _flags_dev(flags, N)
     if out_off is None:
         out_off = batch_out_offsets(DIR_ENCODE, in_off, flags, stream)
+    else:
+        _i64_slots(out_off, N, "out_off")
     if dst is None:
         tot = int(out_off[-1].item()) if total_out is None else int(total_out)
         dst = torch.empty(max(tot, 1), dtype=torch.uint8, device=dev)
     if out_len is None:
         out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    _i64_slots(out_len, N, "out_len")
+    _dev_u8(dst, "dst")
     if validate:
         _validate_packed(src, in_off, out_off, dst, DIR_ENCODE, flags)
     ws = _ws(workspace, N, dev)
@@ -256,8 +291,11 @@ def decode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
     in_off = _i64_dev(in_off, "in_off")
     N = in_off.numel() - 1
     dev = src.device
+    flags = _flags_dev(flags, N)
     if out_off is None:
         out_off = batch_out_offsets(DIR_DECODE, in_off, flags, stream)
+    else:
+        _i64_slots(out_off, N, "out_off")
     if dst is None:
         tot = int(out_off[-1].item()) if total_out is None else int(total_out)
         dst = torch.empty(max(tot, 1), dtype=torch.uint8, device=dev)
@@ -265,6 +303,9 @@ def decode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
         out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
     if err_off is None:
         err_off = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    _i64_slots(out_len, N, "out_len")
+    _i64_slots(err_off, N, "err_off")
+    _dev_u8(dst, "dst")
     if validate:
         _validate_packed(src, in_off, out_off, dst, DIR_DECODE, flags)
     ws = _ws(workspace, N, dev)
@@ -332,13 +373,20 @@ def encode_batch_gather(src, in_begin, in_len, out_off=None, flags=None, dst=Non
     in_begin = _i64_dev(in_begin, "in_begin")
     in_len = _i64_dev(in_len, "in_len")
     N = in_begin.numel()
+    if in_len.numel() != N:
+        raise ValueError("in_begin and in_len differ in length")
     dev = src.device
+    flags = _flags_dev(flags, N)
     if out_off is None:
         out_off, total = _gather_out_off(in_len, DIR_ENCODE, flags, dev)
         if dst is None:
             dst = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    else:
+        _i64_slots(out_off, N, "out_off")
     if out_len is None:
         out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    _i64_slots(out_len, N, "out_len")
+    _dev_u8(dst, "dst")
     if validate:
         _validate_gather(src, in_begin, in_len, out_off, dst, DIR_ENCODE, flags)
     ws = _ws(workspace, N, dev)
@@ -357,15 +405,23 @@ def decode_batch_gather(src, in_begin, in_len, out_off=None, flags=None, dst=Non
     in_begin = _i64_dev(in_begin, "in_begin")
     in_len = _i64_dev(in_len, "in_len")
     N = in_begin.numel()
+    if in_len.numel() != N:
+        raise ValueError("in_begin and in_len differ in length")
     dev = src.device
+    flags = _flags_dev(flags, N)
     if out_off is None:
         out_off, total = _gather_out_off(in_len, DIR_DECODE, flags, dev)
         if dst is None:
             dst = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    else:
+        _i64_slots(out_off, N, "out_off")
     if out_len is None:
         out_len = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
     if err_off is None:
         err_off = torch.empty(max(N, 1), dtype=torch.int64, device=dev)
+    _i64_slots(out_len, N, "out_len")
+    _i64_slots(err_off, N, "err_off")
+    _dev_u8(dst, "dst")
     if validate:
         _validate_gather(src, in_begin, in_len, out_off, dst, DIR_DECODE, flags)
     ws = _ws(workspace, N, dev)

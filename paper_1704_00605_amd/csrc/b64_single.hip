@@ -210,12 +210,18 @@ int sync_slot(SyncSlot **out)
     HIP_TRY(hipGetDevice(&dev));
     for (auto &s : t_slots)
         if (s.dev == dev) { *out = &s; return B64_OK; }
+    // kept only once every step succeeded (a failed step frees what it got)
     SyncSlot s;
     s.dev = dev;
-    HIP_TRY(hipMalloc((void **)&s.d, 64));
-    HIP_TRY(hipHostMalloc((void **)&s.h, 16, hipHostMallocDefault));
-    unsigned long long init[4] = {ERR_NONE, 0ull, 0ull, 0ull};
-    HIP_TRY(hipMemcpy(s.d, init, sizeof init, hipMemcpyHostToDevice));
+    const unsigned long long init[4] = {ERR_NONE, 0ull, 0ull, 0ull};
+    hipError_t e = hipMalloc((void **)&s.d, 64);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.h, 16, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemcpy(s.d, init, sizeof init, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (s.h) (void)hipHostFree(s.h);
+        if (s.d) (void)hipFree(s.d);
+        return b64i_fail(B64_HIP_ERROR, "synchronous-call slots: %s", hipGetErrorString(e));
+    }
     t_slots.push_back(s);
     *out = &t_slots.back();
     return B64_OK;

@@ -755,11 +755,17 @@ int64_t b64_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
     for (auto &e : t_ws)
         if (e.dev == dev) c = &e;
     if (!c) {
-        t_ws.emplace_back();
+        // kept only once both allocations succeeded
+        WsCache e;
+        e.dev = dev;
+        hipError_t r = hipMalloc((void **)&e.verdict, 16);
+        if (r == hipSuccess) r = hipHostMalloc((void **)&e.h, 16, hipHostMallocDefault);
+        if (r != hipSuccess) {
+            if (e.verdict) (void)hipFree(e.verdict);
+            return b64i_fail(B64_HIP_ERROR, "whitespace-decode slots: %s", hipGetErrorString(r));
+        }
+        t_ws.push_back(e);
         c = &t_ws.back();
-        c->dev = dev;
-        HIP_TRY(hipMalloc((void **)&c->verdict, 16));
-        HIP_TRY(hipHostMalloc((void **)&c->h, 16, hipHostMallocDefault));
     }
     const int64_t need = b64_decode_ws_workspace_bytes(n);
     hipStream_t s = (hipStream_t)stream;

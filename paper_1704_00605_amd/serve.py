@@ -92,6 +92,8 @@ def run(requests, banks, pool, max_batch=2048, tick_us=200, streams=4, capture=F
     ib = np.ascontiguousarray(requests["in_begin"], dtype=np.int64)
     il = np.ascontiguousarray(requests["in_len"], dtype=np.int64)
     fl = np.ascontiguousarray(requests["flags"], dtype=np.uint8)
+    if not all(a.ndim == 1 and a.size == n for a in (t_arr, op, ib, il, fl)):
+        raise ValueError("every per-request array needs one entry per request")
     t_done = np.empty(n, np.float64)
     out_off = np.empty(n, np.int64)
     out_len = np.empty(n, np.int64)

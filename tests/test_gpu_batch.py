@@ -316,6 +316,39 @@ def test_config4_full_size_sampled():
         assert torch.equal(out[oo[i]:oo[i] + lens[i]], src[off[i]:off[i + 1]]), i
 
 
+def test_bindings_reject_bad_arguments_before_launch():
+    """Flags, result and slot arrays of the wrong type or too short for N are
+    refused on the host (the kernels would read or write past them); a valid
+    call still works afterwards."""
+    from paper_1704_00605_amd.graph import BatchGraph
+
+    data, off = packed([5, 7, 0, 12], seed=40)
+    src, in_off = dev(data), dev(off)
+    N = off.size - 1
+    i64 = lambda k: torch.empty(k, dtype=torch.int64, device=DEV)
+    with pytest.raises(TypeError):
+        codec.encode_batch(src, in_off, flags=dev(np.zeros(N, np.int32)))
+    with pytest.raises(ValueError):
+        codec.encode_batch(src, in_off, flags=dev(np.zeros(N - 1, np.uint8)))
+    with pytest.raises(TypeError):
+        codec.batch_out_offsets(E, in_off, flags=dev(np.zeros(N, np.int64)))
+    with pytest.raises(ValueError):
+        codec.encode_batch(src, in_off, out_len=i64(N - 1))
+    with pytest.raises(ValueError):
+        codec.encode_batch(src, in_off, out_off=i64(N - 1))
+    text, toff, _ = codec.encode_batch(src, in_off)
+    with pytest.raises(ValueError):
+        codec.decode_batch(text, toff, err_off=i64(N - 1))
+    with pytest.raises(ValueError):
+        codec.decode_batch_gather(text, toff[:-1].contiguous(), i64(N - 1))
+    with pytest.raises(TypeError):
+        codec.decode_async(text[:8], torch.empty(6, dtype=torch.uint8, device=DEV), i64(4)[::2])
+    oo = codec.batch_out_offsets(D, toff)
+    with pytest.raises(ValueError):
+        BatchGraph(D, text, toff, oo, torch.empty(64, dtype=torch.uint8, device=DEV), i64(N), i64(N - 1))
+    check_encode(data, off)
+
+
 def test_out_offsets_scan_sizes():
     rng = np.random.default_rng(7)
     for N in [0, 1, 2, 1023, 1024, 1025, 5000, 100_000]:

@@ -276,7 +276,7 @@ __device__ __forceinline__ void dec_batch_unit(const uint8_t *__restrict__ src, 
         }
     } else {
         int nout;
-        const int idx = dec_tail(src + r.b + 16 * r.j, (int)(r.n - 16 * r.j), r.n, q, tab, r.fl, &nout);
+        const int idx = dec_tail_inl(src + r.b + 16 * r.j, (int)(r.n - 16 * r.j), r.n, q, tab, r.fl, &nout);
         if (idx >= 0)
             atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)(16 * r.j + idx));
         else

@@ -216,10 +216,12 @@ __device__ __noinline__ int dec_first_bad(uint32_t w0, uint32_t w1, uint32_t w2,
 // check (Appendix A), and writes the decoded bytes to q. Returns the first
 // offending index relative to c (r stands for "length error at n"), or -1;
 // *nout receives the number of bytes written (0 when an error was found).
-// The characters are loaded once into registers.
-__device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64_t n,
-                                     uint8_t *__restrict__ q, const uint8_t *tab, int mode,
-                                     int *nout)
+// The characters are loaded once into registers. Inline form: the batched
+// decode finishes many messages per wave, where a call costs more than the
+// extra code (dec_tail below is the out-of-line form for once-per-launch use).
+__device__ __forceinline__ int dec_tail_inl(const uint8_t *__restrict__ c, int r, int64_t n,
+                                            uint8_t *__restrict__ q, const uint8_t *tab, int mode,
+                                            int *nout)
 {
     uint32_t w[4];
     load_upto16(c, r, w);
@@ -270,6 +272,13 @@ __device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64
     store_upto16(q, o, cnt);
     *nout = cnt;
     return -1;
+}
+
+__device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64_t n,
+                                     uint8_t *__restrict__ q, const uint8_t *tab, int mode,
+                                     int *nout)
+{
+    return dec_tail_inl(c, r, n, q, tab, mode, nout);
 }
 
 // -------------------------------------------- register and pair maps --

@@ -235,3 +235,46 @@ def test_ws_marks_next_to_tile_boundaries(shape):
                 c = a.copy()
                 c[j] = bad
                 check(c)
+
+
+def test_ws_beyond_4gib():
+    """A 4.5 GB MIME text (byte offsets above 2^32): the whitespace-tolerant
+    decode returns the payload; an invalid byte and, separately, a misplaced
+    '=' past 2^32 are reported at their original indexes; sampled lines
+    decode as the oracle decodes them."""
+    n = 3_400_000_001
+    g = torch.Generator(device=DEV)
+    g.manual_seed(12)
+    x = torch.randint(0, 256, (n,), dtype=torch.uint8, device=DEV, generator=g)
+    text = codec.encode(x)
+    m = text.numel()
+    full = m // 76
+    rest = m - full * 76
+    wrapped = torch.empty(m + 2 * (full + (1 if rest else 0)), dtype=torch.uint8, device=DEV)
+    v = wrapped[: full * 78].view(full, 78)
+    v[:, :76] = text[: full * 76].view(full, 76)
+    v[:, 76] = 13
+    v[:, 77] = 10
+    if rest:
+        wrapped[full * 78: full * 78 + rest] = text[full * 76:]
+        wrapped[full * 78 + rest:] = torch.tensor([13, 10], dtype=torch.uint8, device=DEV)
+    del text
+    assert wrapped.numel() > (1 << 32)
+    out, err = codec.decode_ws(wrapped)
+    assert err == -1 and out.numel() == n and torch.equal(out, x)
+    # sampled lines past 2^32 against the oracle
+    for line in (full - 3, (1 << 32) // 78 + 5):
+        seg = wrapped[line * 78: line * 78 + 3 * 78].cpu().numpy()
+        want = oracle.decode_ws(seg)
+        assert want[1] == -1
+        assert np.array_equal(out[line * 57: line * 57 + want[0]].cpu().numpy(), want[2])
+    del out
+    p = (1 << 32) + 78 * 1000 + 17
+    keep = int(wrapped[p].item())
+    wrapped[p] = ord("*")
+    out, err = codec.decode_ws(wrapped)
+    assert out is None and err == p
+    wrapped[p] = ord("=")
+    out, err = codec.decode_ws(wrapped)
+    assert out is None and err == p
+    wrapped[p] = keep

@@ -43,9 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=1024)
     ap.add_argument("--quick", action="store_true",
-                    help="only the timed 1 GiB step (skip the config 1, batched and serving reports)")
+                    help="only the timed 1 GiB step (skip the 1 MiB latency, batched and serving reports)")
     ap.add_argument("--only", default="",
-                    help="comma list of extra reports to run: config1,batched3,batched4,maps,files,mime,serving")
+                    help="comma list of extra reports to run: latency,uneven,heavy,maps,files,mime,serving")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-per-message", action="store_true",
                     help="skip the per-message-launch baseline of the batched reports (for kernel traces)")
@@ -245,17 +245,17 @@ def main():
     del x, out, out_bad, bad, text
     torch.cuda.empty_cache()
     if not args.quick:
-        wanted = set(filter(None, args.only.split(","))) or {"config1", "batched3", "batched4", "maps", "files", "mime", "serving"}
-        if "config1" in wanted:
-            progress("config 1 latency")
-            line["config1_latency"] = report_config1()
-        if "batched3" in wanted:
-            progress("config 3 batched vs per-message")
-            line["batched_config3"] = report_batched(3, not args.no_per_message)
+        wanted = set(filter(None, args.only.split(","))) or {"latency", "uneven", "heavy", "maps", "files", "mime", "serving"}
+        if "latency" in wanted:
+            progress("1 MiB latency")
+            line["latency_1MiB"] = report_latency_1mib()
+        if "uneven" in wanted:
+            progress("100,000 uneven messages, batched vs per-message")
+            line["batched_uneven_100k"] = report_batched("uneven", not args.no_per_message)
             torch.cuda.empty_cache()
-        if "batched4" in wanted:
-            progress("config 4 batched vs per-message (autotuned)")
-            line["batched_config4"] = report_batched(4, not args.no_per_message)
+        if "heavy" in wanted:
+            progress("8,192-message heavy mix, batched vs per-message (autotuned)")
+            line["batched_heavy_mix_8k"] = report_batched("heavy", not args.no_per_message)
             torch.cuda.empty_cache()
         if "maps" in wanted:
             progress("character-map variants of the single-buffer kernels")
@@ -270,8 +270,8 @@ def main():
             line["ws_decode_mime"] = report_ws()
             torch.cuda.empty_cache()
         if "serving" in wanted:
-            progress("config 5 serving")
-            line["serving_config5"] = report_serving(args.serve_seconds)
+            progress("serving, Poisson 200,000 requests/s")
+            line["serving_poisson_200k"] = report_serving(args.serve_seconds)
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(payload, text_h, args.cpu_sample_mib)
@@ -306,7 +306,7 @@ def _wall_ms(fn, reps):
     return float(np.median(ts))
 
 
-def report_config1():
+def report_latency_1mib():
     """1 MiB single buffer (seed 0): launch/latency bound and cache resident."""
     import torch
     from paper_1704_00605_amd import codec, workloads
@@ -339,7 +339,8 @@ def report_config1():
 
 
 def report_batched(which, per_message=True):
-    """Configs 3/4: one persistent launch per direction over the packed batch
+    """The 100,000 uneven messages ("uneven") or the 8,192-message heavy mix
+    ("heavy"): one persistent launch per direction over the packed batch
     (plan + codec kernels, eager and as a HIP graph, default and autotuned
     launch shape) against one single-buffer launch per message."""
     import torch
@@ -348,7 +349,7 @@ def report_batched(which, per_message=True):
 
     dev = torch.device("cuda:0")
     s = torch.cuda.current_stream()
-    if which == 3:
+    if which == "uneven":
         w = workloads.uneven()
         name = "100,000 messages, lengths log-uniform in [1, 65536] (seed 2), standard alphabet, 1% corrupted"
     else:
@@ -589,7 +590,7 @@ def report_ws():
 
 
 def report_serving(seconds):
-    """Config 5: Poisson arrivals at 200,000/s, 50/50 encode/decode, sizes
+    """Serving: Poisson arrivals at 200,000/s, 50/50 encode/decode, sizes
     log-uniform in [64 B, 1 MiB], 1% of decodes corrupted; device pool capped
     at 8 GiB with admission by free memory."""
     import torch

@@ -238,7 +238,7 @@ def test_per_message_modes_in_batch():
             assert np.array_equal(d[oo[i]:oo[i] + w[0]], w[2])
 
 
-def test_config3_uneven_100k_messages():
+def test_uneven_100k_messages():
     w = workloads.uneven()
     data, off = w["payload"], w["in_off"]
     assert off.size == 100_001
@@ -253,7 +253,7 @@ def test_config3_uneven_100k_messages():
         assert ge[m_id] >= 0 and ge[m_id] <= pos
 
 
-def test_config4_shaped_heavy_mix_scaled():
+def test_heavy_mix_scaled():
     """The heavy-tailed mix with per-message alphabets at reduced count
     (large messages 1-4 MiB) so the oracle finishes in seconds."""
     w = workloads.heavy_mix(count=1024, n_large=102, large=(1 << 20, 4 << 20), seed=3)
@@ -264,7 +264,7 @@ def test_config4_shaped_heavy_mix_scaled():
     check_decode(text, toff, flags)
 
 
-def test_config4_full_size_sampled():
+def test_heavy_mix_8192_full_size_sampled():
     """The heavy-tailed mix at full size (8,192 messages, 7.25 GB, per-message
     alphabets, 41 corrupted) in the autotuned launch shape, as timed: every
     length and verdict against its closed form or the oracle, the corrupted

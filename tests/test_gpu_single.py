@@ -196,7 +196,7 @@ def test_all_2_24_triples_closed_form():
         assert err == -1 and torch.equal(out, dev(buf))
 
 
-def test_config1_one_mib_seed0():
+def test_one_mib_seed0():
     w = workloads.single(1 << 20, seed=0)
     x = w["payload"]
     t = codec.encode(dev(x))
@@ -213,7 +213,7 @@ def test_config1_one_mib_seed0():
     assert (out, err) == (None, pos)
 
 
-def test_config2_one_gib_sampled():
+def test_one_gib_sampled():
     """1 GiB at the benchmark's launch shape: round trip checked on the
     device, sampled windows and the tail checked against the oracle, and the
     injected byte at 99.9% of the text found at exactly its offset."""

@@ -36,10 +36,16 @@
  *       B64_POOL_FULL (-4) a pool allocation found no free block (pools);
  *       B64_TIMEOUT (-5) the serving loop hit its time limit.
  *     b64_last_error() describes the most recent failure on this thread.
- *   - No entry point allocates device memory during the call except the
- *     synchronous b64_decode / b64_decode_ex, which on first use on a thread
- *     and device allocate (once) a 64-byte result slot and a pinned
- *     readback word that are then reused.
+ *   - Entry points allocate no device memory, except:
+ *       b64_decode / b64_decode_ex: on first use on a thread and device,
+ *         a 64-byte result slot and a pinned readback word, then reused;
+ *       b64_decode_ws: per thread and device, its verdict slots (once) and
+ *         a workspace grown to the largest input seen;
+ *       b64_batch_out_offsets: stream-ordered partial sums (hipMallocAsync,
+ *         freed on the same stream) for each call;
+ *       b64_graph_create_batch: a private capture stream and the graph;
+ *       b64_server_run: per-stream staging buffers, freed before it returns.
+ *     The asynchronous and batched calls take caller-owned workspaces.
  */
 #ifndef B64HIP_H
 #define B64HIP_H

@@ -71,8 +71,10 @@ def load_cache():
 
 
 def save_cache(c):
+    """Atomic replace through a per-process temporary file, so that processes
+    saving at once never interleave their writes (the last one wins)."""
     p = cache_path()
-    tmp = p + ".tmp"
+    tmp = f"{p}.{os.getpid()}.tmp"
     with open(tmp, "w") as f:
         json.dump(c, f, indent=1)
     os.replace(tmp, p)

@@ -343,6 +343,24 @@ def test_appendix_a_strict_checks():
         assert err == -1 and np.array_equal(y, x)
 
 
+@pytest.mark.parametrize("alphabet", [STD, URL])
+def test_appendix_a_strict_accepts_exactly_the_canonical_texts(table1, alphabet):
+    """Appendix A's checks make the decode injective: a padded text passes
+    them exactly when encoding its decoded bytes gives the text back. Every
+    symbol in the position holding the leftover bits, for both endings; the
+    plain decode accepts all of them."""
+    sym = b64sym_table(table1, alphabet)
+    for v in range(64):
+        for t in (bytes([sym[5], sym[v]]) + b"==", bytes([sym[5], sym[9], sym[v]]) + b"="):
+            m, err, y = oracle.decode(t, alphabet)
+            assert err == -1
+            canonical = bytes(oracle.encode(y, alphabet)) == t
+            ms, errs, _ = oracle.decode_strict(t, alphabet)
+            assert (errs == -1) == canonical, (v, t)
+            if not canonical:
+                assert errs == len(t) - (3 if t.endswith(b"==") else 2)
+
+
 # ------------------------------------------------ independent library check --
 
 @settings(max_examples=300, deadline=None)

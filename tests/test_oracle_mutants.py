@@ -39,6 +39,19 @@ MUTANTS = {
                             "if (len < 0) *err_off = (*err_off >= m) ? n : *err_off;"),
     "ws_length_error_at_m": ("if (len < 0) *err_off = (*err_off >= m) ? n : pos[*err_off];",
                              "if (len < 0) *err_off = (*err_off >= m) ? m : pos[*err_off];"),
+    # Appendix A strict checks and the unpadded mode
+    "strict_two_pad_bits": ("if ((inv[c[n - 3]] * 16) % 256 != 0)", "if ((inv[c[n - 3]] * 64) % 256 != 0)"),
+    "strict_one_pad_bits": ("if ((inv[c[n - 2]] * 64) % 256 != 0)", "if ((inv[c[n - 2]] * 16) % 256 != 0)"),
+    "nopad_accepts_len_mod4_1": ("    if (bad < 0 && n % 4 == 1) bad = n;\n    if (bad >= 0) { *err_off = bad; return -1; }",
+                                 "    if (bad >= 0) { *err_off = bad; return -1; }"),
+    "nopad_second_byte": ("p[o++] = (uint8_t)(((b * 16) % 256) + (cc / 4));\n        }\n    }\n    return o;",
+                          "p[o++] = (uint8_t)(((b * 16) % 256) + (cc / 2));\n        }\n    }\n    return o;"),
+    # batch loops
+    "batch_encode_ignores_flags": ("dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
+                                   "dst + out_off[i],\n                                   ORACLE_STD);"),
+    "batch_decode_ignores_flags": ("flags ? flags[i] : ORACLE_STD, &err_off[i]);", "ORACLE_STD, &err_off[i]);"),
+    "batch_output_at_input_offset": ("in_off[i + 1] - in_off[i], dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
+                                     "in_off[i + 1] - in_off[i], dst + in_off[i],\n                                   flags ? flags[i] : ORACLE_STD);"),
 }
 
 PIN_TESTS = [
@@ -56,6 +69,9 @@ PIN_TESTS = [
     lambda t1: pins.test_single_injected_offset_is_exact(),
     lambda t1: pins.test_whitespace_strip_and_decode(),
     lambda t1: pins.test_whitespace_mode_classifies_every_byte_value(),
+    lambda t1: pins.test_appendix_a_strict_checks(),
+    lambda t1: pins.test_appendix_a_strict_accepts_exactly_the_canonical_texts(t1, oracle.STD),
+    lambda t1: pins.test_nopad_variants(),
 ]
 
 

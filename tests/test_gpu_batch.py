@@ -14,7 +14,8 @@ E, D = codec.DIR_ENCODE, codec.DIR_DECODE
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a if a.flags.writeable else a.copy()).to(DEV)
 
 
 def host(t):

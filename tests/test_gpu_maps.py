@@ -23,7 +23,8 @@ def restore_defaults():
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a if a.flags.writeable else a.copy()).to(DEV)
 
 
 @pytest.mark.parametrize("grid", [-1, 8])

@@ -25,7 +25,8 @@ SIZES = sorted(set(list(range(0, 70)) + [95, 96, 97, 767, 768, 769, 1023, 1024, 
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a if a.flags.writeable else a.copy()).to(DEV)
 
 
 def host(t):
@@ -81,6 +82,40 @@ def test_decode_unpadded_and_strict():
         want = oracle.decode_nopad(s)
         out, err = codec.decode(dev(np.frombuffer(s, np.uint8)), STD | NOPAD)
         assert (out.numel() if out is not None else -1, err) == want[:2], s
+
+
+@pytest.mark.parametrize("alphabet", [STD, URL])
+def test_strict_mode_every_leftover_symbol(alphabet):
+    """Appendix A on the GPU: every symbol in the position holding the
+    leftover bits, for both padded endings, after 0, 3 and 4 full quads (the
+    final quad in different places of a 16-character unit), as one batched
+    decode with per-message strict flags and as single-buffer calls; verdicts,
+    lengths and bytes equal the oracle's strict decode."""
+    syms = [oracle.symbol(v, alphabet) for v in range(64)]
+    rng = np.random.default_rng(40 + alphabet)
+    msgs = []
+    for k in (0, 3, 4):
+        prefix = bytes(oracle.encode(rng.integers(0, 256, 3 * k, dtype=np.uint8), alphabet))
+        for v in range(64):
+            msgs.append(prefix + bytes([syms[5], syms[v]]) + b"==")
+            msgs.append(prefix + bytes([syms[5], syms[9], syms[v]]) + b"=")
+    text = np.frombuffer(b"".join(msgs), np.uint8).copy()
+    toff = np.zeros(len(msgs) + 1, np.int64)
+    np.cumsum([len(m) for m in msgs], out=toff[1:])
+    flags = np.full(len(msgs), alphabet | codec.FLAG_STRICT, np.uint8)
+    out, oo, gl, ge = codec.decode_batch(dev(text), dev(toff), flags=dev(flags))
+    gl, ge, oo, ob = host(gl), host(ge), host(oo), host(out)
+    n_bad = 0
+    for i, m in enumerate(msgs):
+        want = oracle.decode_strict(np.frombuffer(m, np.uint8), alphabet)
+        assert (gl[i], ge[i]) == want[:2], (i, m)
+        if want[0] >= 0:
+            assert bytes(ob[oo[i]:oo[i] + want[0]]) == bytes(want[2])
+        n_bad += want[0] < 0
+        if i % 7 == 0:
+            got, err = codec.decode(dev(np.frombuffer(m, np.uint8)), alphabet | STRICT)
+            assert (-1 if got is None else got.numel(), err) == want[:2], m
+    assert 0 < n_bad < len(msgs)
 
 
 def test_padding_and_length_readings():

@@ -14,7 +14,8 @@ SHAPES = [(256, 1), (256, 2), (256, 4), (256, 8), (512, 1), (512, 2), (512, 4), 
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a if a.flags.writeable else a.copy()).to(DEV)
 
 
 def gpu_ws(a, alphabet=0, shift=0):

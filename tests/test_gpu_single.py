@@ -118,6 +118,37 @@ def test_strict_mode_every_leftover_symbol(alphabet):
     assert 0 < n_bad < len(msgs)
 
 
+@pytest.mark.parametrize("alphabet", [STD, URL])
+def test_unpadded_mode_every_final_symbol(alphabet):
+    """The unpadded mode (Section 2) on the GPU: every symbol as the last
+    character of a final group of 2 or 3 characters (leftover bits accepted,
+    as in the padded mode without Appendix A), after 0, 3 and 4 full quads,
+    as one batched decode whose messages also carry the strict flag (ignored
+    for unpadded messages) and as single-buffer calls; equal to the oracle's
+    unpadded decode."""
+    syms = [oracle.symbol(v, alphabet) for v in range(64)]
+    rng = np.random.default_rng(50 + alphabet)
+    msgs = []
+    for k in (0, 3, 4):
+        prefix = bytes(oracle.encode(rng.integers(0, 256, 3 * k, dtype=np.uint8), alphabet))
+        for v in range(64):
+            msgs.append(prefix + bytes([syms[5], syms[v]]))
+            msgs.append(prefix + bytes([syms[5], syms[9], syms[v]]))
+    text = np.frombuffer(b"".join(msgs), np.uint8).copy()
+    toff = np.zeros(len(msgs) + 1, np.int64)
+    np.cumsum([len(m) for m in msgs], out=toff[1:])
+    flags = np.full(len(msgs), alphabet | codec.FLAG_NOPAD | codec.FLAG_STRICT, np.uint8)
+    out, oo, gl, ge = codec.decode_batch(dev(text), dev(toff), flags=dev(flags))
+    gl, ge, oo, ob = host(gl), host(ge), host(oo), host(out)
+    for i, m in enumerate(msgs):
+        want = oracle.decode_nopad(np.frombuffer(m, np.uint8), alphabet)
+        assert want[1] == -1 and (gl[i], ge[i]) == want[:2], (i, m)
+        assert bytes(ob[oo[i]:oo[i] + want[0]]) == bytes(want[2])
+        if i % 7 == 0:
+            got, err = codec.decode(dev(np.frombuffer(m, np.uint8)), alphabet | NOPAD)
+            assert err == -1 and bytes(host(got)) == bytes(want[2]), m
+
+
 def test_padding_and_length_readings():
     cases = [b"", b"Zg==", b"Zh==", b"Zm8=", b"Zg==AAAA", b"AB=C", b"Zg=", b"Z===", b"====",
              b"=AAA", b"A", b"AB", b"ABC", b"AB\x80D", b"AB D", b"A@C", b"QUJD" * 4 + b"Zg==",

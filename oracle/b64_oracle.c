@@ -28,8 +28,9 @@
  *       separate function.
  *   R5  Each alphabet accepts only its own 64 symbols.
  *
- * Every routine here is a direct, unoptimised restatement: per-character loops
- * and the paper's integer operations (div, times, mod) written out.
+ * Every routine here is a direct, unoptimised restatement of a definition:
+ * per-group and per-character loops over 24-bit group values and their 6-bit
+ * fields, with no blocking or table tricks.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -80,29 +81,28 @@ int oracle_value(int alphabet, int ch)
 
 int64_t oracle_encoded_len(int64_t n) { return n <= 0 ? 0 : 4 * ((n + 2) / 3); }
 
-/* Algorithm 1. s[0..n) -> p, returns the number of characters written. */
+/* Encoding (Section 2, Algorithm 1). Every group of three bytes, read most
+ * significant first, is one 24-bit number; its four 6-bit fields, from the
+ * top, are mapped through B. A final group of r = n mod 3 bytes (1 or 2) is
+ * read as a 24-bit number whose missing low bytes are zero: its first r + 1
+ * fields are mapped through B and the remaining 3 - r characters are '=',
+ * so the output always has 4 * ceil(n / 3) characters. Returns that number. */
+static uint32_t oracle_group(const uint8_t *s, int64_t avail)
+{
+    uint32_t v = 0;
+    for (int k = 0; k < 3; k++) v = (v << 8) | (k < avail ? s[k] : 0u);
+    return v;
+}
+
+static unsigned oracle_field(uint32_t v, int k) { return (v >> (18 - 6 * k)) & 63u; }
+
 int64_t oracle_encode(const uint8_t *s, int64_t n, uint8_t *p, int alphabet)
 {
-    int64_t o = 0, i;
-    if (n <= 0) return 0;
-    /* main loop: i = 0, 3, ..., n - (n mod 3) - 3 */
-    for (i = 0; i + 3 <= n - (n % 3); i += 3) {
-        p[o++] = oracle_B(alphabet, s[i] / 4);
-        p[o++] = oracle_B(alphabet, ((s[i] * 16) % 64) + (s[i + 1] / 16));
-        p[o++] = oracle_B(alphabet, ((s[i + 1] * 4) % 64) + (s[i + 2] / 64));
-        p[o++] = oracle_B(alphabet, s[i + 2] % 64);
-    }
-    i = n - n % 3;
-    if (i < n) {
-        p[o++] = oracle_B(alphabet, s[i] / 4);
-        if (i == n - 1) {
-            p[o++] = oracle_B(alphabet, (s[i] * 16) % 64);
-            p[o++] = '=';
-        } else { /* i == n - 2 */
-            p[o++] = oracle_B(alphabet, ((s[i] * 16) % 64) + (s[i + 1] / 16));
-            p[o++] = oracle_B(alphabet, (s[i + 1] * 4) % 64);
-        }
-        p[o++] = '=';
+    int64_t o = 0;
+    for (int64_t g = 0; g < n; g += 3) {
+        const int64_t avail = n - g < 3 ? n - g : 3;
+        const uint32_t v = oracle_group(s + g, avail);
+        for (int k = 0; k < 4; k++) p[o++] = k <= avail ? oracle_B(alphabet, oracle_field(v, k)) : (uint8_t)'=';
     }
     return o;
 }
@@ -126,26 +126,30 @@ static int64_t oracle_first_bad(const uint8_t *c, int64_t n, int64_t begin, int6
     return -1;
 }
 
-/* Algorithm 2 body on the quads whose first character lies in [qbegin, qend)
- * (multiples of 4), for an input already validated. The padding character
- * counts as 0 and stops the output, as in Algorithm 2. Returns the number of
- * bytes appended at p. */
+/* Decoding of a validated text (Section 2, Algorithm 2): each quad of
+ * characters is one 24-bit number, the values of its four characters placed
+ * from the top in 6-bit fields ('=' counts as 0), and its three bytes, most
+ * significant first, are the output. Quads start at qbegin, qbegin + 4, ...
+ * below qend. Writes all three bytes of every quad and returns their number;
+ * the caller drops one byte per trailing '='. */
 static int64_t oracle_decode_quads(const uint8_t *c, int64_t qbegin, int64_t qend, uint8_t *p,
                                    const int inv[256])
 {
     int64_t o = 0;
     for (int64_t i = qbegin; i < qend; i += 4) {
-        int a = c[i + 0] == '=' ? 0 : inv[c[i + 0]];
-        int b = c[i + 1] == '=' ? 0 : inv[c[i + 1]];
-        int cc = c[i + 2] == '=' ? 0 : inv[c[i + 2]];
-        int d = c[i + 3] == '=' ? 0 : inv[c[i + 3]];
-        p[o++] = (uint8_t)((a * 4) + (b / 16));
-        if (c[i + 2] == '=') return o;
-        p[o++] = (uint8_t)(((b * 16) % 256) + (cc / 4));
-        if (c[i + 3] == '=') return o;
-        p[o++] = (uint8_t)(((cc * 64) % 256) + d);
+        uint32_t v = 0;
+        for (int k = 0; k < 4; k++) v = (v << 6) | (c[i + k] == '=' ? 0u : (uint32_t)inv[c[i + k]]);
+        for (int k = 0; k < 3; k++) p[o++] = (uint8_t)(v >> (16 - 8 * k));
     }
     return o;
+}
+
+/* Number of '=' ending c[0..n) (0, 1 or 2 for a validated text). */
+static int64_t oracle_pads(const uint8_t *c, int64_t n)
+{
+    int64_t k = 0;
+    while (k < 2 && k < n && c[n - 1 - k] == '=') k++;
+    return k;
 }
 
 int64_t oracle_decoded_max(int64_t m) { return m <= 0 ? 0 : 3 * (m / 4); }
@@ -166,24 +170,24 @@ int64_t oracle_decode(const uint8_t *c, int64_t n, uint8_t *p, int alphabet, int
         *err_off = bad;
         return -1;
     }
-    return oracle_decode_quads(c, 0, n, p, inv);
+    return oracle_decode_quads(c, 0, n, p, inv) - oracle_pads(c, n);
 }
 
-/* Appendix A: additional checks on the last quad. With two '=' the value of
- * C[n-3] times 16 must be 0 mod 256; with one '=' the value of C[n-2] times 64
- * must be 0 mod 256. A failure is reported at that character's index. Applied
- * after oracle_decode succeeds. */
+/* Appendix A: additional checks on the last quad. A padded final quad
+ * carries bits that fall into the bytes its '=' characters drop: the low four
+ * bits of the value of C[n-3] when it ends in "==", the low two bits of the
+ * value of C[n-2] when it ends in one '='. They must be zero; otherwise the
+ * error is reported at that character's index. Applied after oracle_decode
+ * succeeds. */
 int64_t oracle_decode_strict(const uint8_t *c, int64_t n, uint8_t *p, int alphabet, int64_t *err_off)
 {
     int inv[256];
-    int64_t len = oracle_decode(c, n, p, alphabet, err_off);
+    int64_t len = oracle_decode(c, n, p, alphabet, err_off), pads;
     if (len < 0 || n == 0) return len;
     oracle_build_A(alphabet, inv);
-    if (c[n - 1] == '=' && c[n - 2] == '=') {
-        if ((inv[c[n - 3]] * 16) % 256 != 0) { *err_off = n - 3; return -1; }
-    } else if (c[n - 1] == '=') {
-        if ((inv[c[n - 2]] * 64) % 256 != 0) { *err_off = n - 2; return -1; }
-    }
+    pads = oracle_pads(c, n);
+    if (pads == 2 && (inv[c[n - 3]] & 15) != 0) { *err_off = n - 3; return -1; }
+    if (pads == 1 && (inv[c[n - 2]] & 3) != 0) { *err_off = n - 2; return -1; }
     return len;
 }
 
@@ -199,12 +203,13 @@ int64_t oracle_encode_nopad(const uint8_t *s, int64_t n, uint8_t *p, int alphabe
 
 /* Unpadded decode: the input is the padded form with its '=' removed, so its
  * length mod 4 is 0, 2 or 3; 1 is an error at offset n. '=' is invalid
- * everywhere. The last 2 or 3 characters decode to 1 or 2 bytes as Algorithm 2
- * does for a padded final quad. */
+ * everywhere. A trailing group of r = n mod 4 characters (2 or 3) is read as
+ * a quad whose missing characters are 0, and its first r - 1 bytes are the
+ * output, as for a padded final quad. */
 int64_t oracle_decode_nopad(const uint8_t *c, int64_t n, uint8_t *p, int alphabet, int64_t *err_off)
 {
     int inv[256];
-    int64_t bad = -1, full, o;
+    int64_t bad = -1, full, o, r;
     *err_off = -1;
     if (n <= 0) return 0;
     oracle_build_A(alphabet, inv);
@@ -214,13 +219,11 @@ int64_t oracle_decode_nopad(const uint8_t *c, int64_t n, uint8_t *p, int alphabe
     if (bad >= 0) { *err_off = bad; return -1; }
     full = n - n % 4;
     o = oracle_decode_quads(c, 0, full, p, inv);
-    if (n % 4 >= 2) {
-        int a = inv[c[full]], b = inv[c[full + 1]];
-        p[o++] = (uint8_t)((a * 4) + (b / 16));
-        if (n % 4 == 3) {
-            int cc = inv[c[full + 2]];
-            p[o++] = (uint8_t)(((b * 16) % 256) + (cc / 4));
-        }
+    r = n - full;
+    if (r >= 2) {
+        uint32_t v = 0;
+        for (int64_t k = 0; k < 4; k++) v = (v << 6) | (k < r ? (uint32_t)inv[c[full + k]] : 0u);
+        for (int64_t k = 0; k < r - 1; k++) p[o++] = (uint8_t)(v >> (16 - 8 * k));
     }
     return o;
 }
@@ -340,7 +343,7 @@ static int64_t oracle_run_pieces(int dir, const uint8_t *src, int64_t n, uint8_t
     if (dir == 0) return total;
     if (bad < 0 && n % 4 != 0) bad = n;
     *err_off = bad;
-    return bad >= 0 ? -1 : total;
+    return bad >= 0 ? -1 : total - oracle_pads(src, n);
 }
 
 int64_t oracle_encode_mt(const uint8_t *s, int64_t n, uint8_t *p, int alphabet, int threads)

@@ -14,23 +14,28 @@ from oracle import build as obuild
 import test_oracle as pins
 
 MUTANTS = {
-    "enc_second_shift": ("(s[i + 1] / 16));\n        p[o++] = oracle_B(alphabet, ((s[i + 1] * 4)",
-                         "(s[i + 1] / 8));\n        p[o++] = oracle_B(alphabet, ((s[i + 1] * 4)"),
-    "enc_drop_third_term": ("+ (s[i + 2] / 64));", ");"),
+    # encoding: group value, 6-bit fields, padding
+    "enc_field_mask": ("return (v >> (18 - 6 * k)) & 63u;", "return (v >> (18 - 6 * k)) & 31u;"),
+    "enc_field_shift": ("return (v >> (18 - 6 * k)) & 63u;", "return (v >> (18 - 5 * k)) & 63u;"),
+    "enc_group_little_endian": ("v = (v << 8) | (k < avail ? s[k] : 0u);",
+                                "v = (v >> 8) | ((k < avail ? s[k] : 0u) << 16);"),
+    "enc_drop_third_byte": ("for (int k = 0; k < 3; k++) v = (v << 8)", "for (int k = 0; k < 2; k++) v = (v << 8)"),
+    "enc_missing_bytes_not_zero": ("(k < avail ? s[k] : 0u)", "(k < avail ? s[k] : 0xffu)"),
     "table_swap_62_63": ('"+/";', '"/+";'),
     "url_swap": ("if (v == 62) return (uint8_t)'-';", "if (v == 62) return (uint8_t)'_';"),
-    "tail1_shift": ("p[o++] = oracle_B(alphabet, (s[i] * 16) % 64);",
-                    "p[o++] = oracle_B(alphabet, (s[i] * 4) % 64);"),
-    "drop_one_pad": ("        }\n        p[o++] = '=';\n    }\n    return o;", "        }\n    }\n    return o;"),
-    "dec_first_byte": ("(uint8_t)((a * 4) + (b / 16));\n        if (c[i + 2]",
-                       "(uint8_t)((a * 4) + (b / 8));\n        if (c[i + 2]"),
-    "dec_third_byte": ("(uint8_t)(((cc * 64) % 256) + d);\n    }", "(uint8_t)(((cc * 16) % 256) + d);\n    }"),
+    "drop_one_pad": ("p[o++] = k <= avail ?", "p[o++] = k <= avail + 1 ?"),
+    "one_field_short": ("p[o++] = k <= avail ?", "p[o++] = k < avail ?"),
+    # decoding: group value, byte order, padding, validation
+    "dec_field_shift": ("v = (v << 6) | (c[i + k] == '='", "v = (v << 5) | (c[i + k] == '='"),
+    "dec_bytes_little_endian": ("for (int k = 0; k < 3; k++) p[o++] = (uint8_t)(v >> (16 - 8 * k));",
+                                "for (int k = 0; k < 3; k++) p[o++] = (uint8_t)(v >> (8 * k));"),
+    "dec_pads_not_dropped": ("return oracle_decode_quads(c, 0, n, p, inv) - oracle_pads(c, n);",
+                             "return oracle_decode_quads(c, 0, n, p, inv);"),
     "pad_slot2_relaxed": ("if (i == n - 2 && c[n - 1] == '=') return 1;", "if (i == n - 2) return 1;"),
     "no_length_check": ("if (bad < 0 && n % 4 != 0) bad = n;\n    if (bad >= 0) {\n        *err_off",
                         "if (bad >= 0) {\n        *err_off"),
     "offset_off_by_one": ("if (!oracle_char_ok(c, n, i, inv)) return i;",
                           "if (!oracle_char_ok(c, n, i, inv)) return i + 1;"),
-    "dec_no_early_stop": ("        if (c[i + 2] == '=') return o;\n", ""),
     # whitespace-tolerant decode (Appendix B)
     "ws_also_tab": ("if (v == ' ' || v == '\\n' || v == '\\r') continue;",
                     "if (v == ' ' || v == '\\n' || v == '\\r' || v == '\\t') continue;"),
@@ -40,12 +45,11 @@ MUTANTS = {
     "ws_length_error_at_m": ("if (len < 0) *err_off = (*err_off >= m) ? n : pos[*err_off];",
                              "if (len < 0) *err_off = (*err_off >= m) ? m : pos[*err_off];"),
     # Appendix A strict checks and the unpadded mode
-    "strict_two_pad_bits": ("if ((inv[c[n - 3]] * 16) % 256 != 0)", "if ((inv[c[n - 3]] * 64) % 256 != 0)"),
-    "strict_one_pad_bits": ("if ((inv[c[n - 2]] * 64) % 256 != 0)", "if ((inv[c[n - 2]] * 16) % 256 != 0)"),
+    "strict_two_pad_bits": ("(inv[c[n - 3]] & 15) != 0", "(inv[c[n - 3]] & 3) != 0"),
+    "strict_one_pad_bits": ("(inv[c[n - 2]] & 3) != 0", "(inv[c[n - 2]] & 15) != 0"),
     "nopad_accepts_len_mod4_1": ("    if (bad < 0 && n % 4 == 1) bad = n;\n    if (bad >= 0) { *err_off = bad; return -1; }",
                                  "    if (bad >= 0) { *err_off = bad; return -1; }"),
-    "nopad_second_byte": ("p[o++] = (uint8_t)(((b * 16) % 256) + (cc / 4));\n        }\n    }\n    return o;",
-                          "p[o++] = (uint8_t)(((b * 16) % 256) + (cc / 2));\n        }\n    }\n    return o;"),
+    "nopad_tail_one_byte_short": ("for (int64_t k = 0; k < r - 1; k++) p[o++]", "for (int64_t k = 0; k < r - 2; k++) p[o++]"),
     # batch loops
     "batch_encode_ignores_flags": ("dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
                                    "dst + out_off[i],\n                                   ORACLE_STD);"),

@@ -56,6 +56,10 @@ def lib():
             "oracle_decode_ws": (i64, [p, i64, p, i32, pi64]),
             "oracle_encode_batch": (None, [p, p, i64, p, p, p, p]),
             "oracle_decode_batch": (None, [p, p, i64, p, p, p, p, p]),
+            "oracle_encode_batch_mt": (None, [p, p, i64, p, p, p, p, i32]),
+            "oracle_decode_batch_mt": (None, [p, p, i64, p, p, p, p, p, i32]),
+            "oracle_encode_gather_mt": (None, [p, p, p, i64, p, p, p, p, i32]),
+            "oracle_decode_gather_mt": (None, [p, p, p, i64, p, p, p, p, p, i32]),
             "oracle_encode_mt": (i64, [p, i64, p, i32, i32]),
             "oracle_decode_mt": (i64, [p, i64, p, i32, i32, pi64]),
         }
@@ -154,8 +158,9 @@ def decode_ws(data, alphabet=STD):
     return _dec(lib().oracle_decode_ws, data, alphabet)
 
 
-def encode_batch(src, in_off, flags=None):
-    """Plain loop over messages. Returns (dst, out_off, out_len)."""
+def encode_batch(src, in_off, flags=None, threads=1):
+    """Plain loop over messages (split over ``threads`` host threads by
+    contiguous message ranges). Returns (dst, out_off, out_len)."""
     src = _u8(src)
     in_off = np.ascontiguousarray(in_off, dtype=np.int64)
     N = in_off.size - 1
@@ -165,13 +170,18 @@ def encode_batch(src, in_off, flags=None):
     dst = np.zeros(max(int(out_off[-1]), 1), dtype=np.uint8)
     out_len = np.empty(max(N, 1), dtype=np.int64)
     fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
-    lib().oracle_encode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off),
-                              None if fl is None else _ptr(fl), _ptr(out_len))
+    if threads > 1:
+        lib().oracle_encode_batch_mt(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off),
+                                     None if fl is None else _ptr(fl), _ptr(out_len), int(threads))
+    else:
+        lib().oracle_encode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off),
+                                  None if fl is None else _ptr(fl), _ptr(out_len))
     return dst[: out_off[-1]], out_off, out_len[:N]
 
 
-def decode_batch(src, in_off, flags=None):
-    """Plain loop over messages. Returns (dst, out_off, out_len, err_off);
+def decode_batch(src, in_off, flags=None, threads=1):
+    """Plain loop over messages (split over ``threads`` host threads by
+    contiguous message ranges). Returns (dst, out_off, out_len, err_off);
     out_off holds capacity slots of 3 * floor(len / 4) bytes."""
     src = _u8(src)
     in_off = np.ascontiguousarray(in_off, dtype=np.int64)
@@ -183,9 +193,52 @@ def decode_batch(src, in_off, flags=None):
     out_len = np.empty(max(N, 1), dtype=np.int64)
     err = np.empty(max(N, 1), dtype=np.int64)
     fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
-    lib().oracle_decode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off),
-                              None if fl is None else _ptr(fl), _ptr(out_len), _ptr(err))
+    if threads > 1:
+        lib().oracle_decode_batch_mt(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off),
+                                     None if fl is None else _ptr(fl), _ptr(out_len), _ptr(err),
+                                     int(threads))
+    else:
+        lib().oracle_decode_batch(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off),
+                                  None if fl is None else _ptr(fl), _ptr(out_len), _ptr(err))
     return dst[: out_off[-1]], out_off, out_len[:N], err[:N]
+
+
+def encode_gather(src, in_begin, in_len, out_off, dst, flags=None, threads=1):
+    """Message i is src[in_begin[i], in_begin[i] + in_len[i]); its characters
+    are written to dst[out_off[i]:] (caller-sized host array). Returns the
+    per-message lengths."""
+    src = _u8(src)
+    ib = np.ascontiguousarray(in_begin, dtype=np.int64)
+    il = np.ascontiguousarray(in_len, dtype=np.int64)
+    oo = np.ascontiguousarray(out_off, dtype=np.int64)
+    N = ib.size
+    if il.size != N or oo.size < N or np.any(il < 0) or np.any(ib < 0) or np.any(ib + il > src.size) \
+            or np.any(oo + 4 * ((il + 2) // 3) > dst.size):
+        raise ValueError("message spans or output slots out of range")
+    out_len = np.empty(max(N, 1), dtype=np.int64)
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    lib().oracle_encode_gather_mt(_ptr(src), _ptr(ib), _ptr(il), N, _ptr(dst), _ptr(oo),
+                                  None if fl is None else _ptr(fl), _ptr(out_len), int(threads))
+    return out_len[:N]
+
+
+def decode_gather(src, in_begin, in_len, out_off, dst, flags=None, threads=1):
+    """Validating decode of messages src[in_begin[i], in_begin[i] + in_len[i])
+    into dst[out_off[i]:]. Returns (out_len, err_off) per message."""
+    src = _u8(src)
+    ib = np.ascontiguousarray(in_begin, dtype=np.int64)
+    il = np.ascontiguousarray(in_len, dtype=np.int64)
+    oo = np.ascontiguousarray(out_off, dtype=np.int64)
+    N = ib.size
+    if il.size != N or oo.size < N or np.any(il < 0) or np.any(ib < 0) or np.any(ib + il > src.size) \
+            or np.any(oo + 3 * (il // 4) > dst.size):
+        raise ValueError("message spans or output slots out of range")
+    out_len = np.empty(max(N, 1), dtype=np.int64)
+    err = np.empty(max(N, 1), dtype=np.int64)
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    lib().oracle_decode_gather_mt(_ptr(src), _ptr(ib), _ptr(il), N, _ptr(dst), _ptr(oo),
+                                  None if fl is None else _ptr(fl), _ptr(out_len), _ptr(err), int(threads))
+    return out_len[:N], err[:N]
 
 
 class using:

@@ -358,3 +358,121 @@ int64_t oracle_decode_mt(const uint8_t *c, int64_t n, uint8_t *p, int alphabet, 
     *err_off = -1;
     return n <= 0 ? 0 : oracle_run_pieces(1, c, n, p, alphabet, threads, err_off);
 }
+
+/* Gather forms: message i is src[in_begin[i] .. in_begin[i] + in_len[i]);
+ * otherwise as the packed forms above. */
+void oracle_encode_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
+                          uint8_t *dst, const int64_t *out_off, const uint8_t *flags, int64_t *out_len)
+{
+    for (int64_t i = 0; i < N; i++)
+        out_len[i] = oracle_encode(src + in_begin[i], in_len[i], dst + out_off[i],
+                                   flags ? flags[i] : ORACLE_STD);
+}
+
+void oracle_decode_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
+                          uint8_t *dst, const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                          int64_t *err_off)
+{
+    for (int64_t i = 0; i < N; i++)
+        out_len[i] = oracle_decode(src + in_begin[i], in_len[i], dst + out_off[i],
+                                   flags ? flags[i] : ORACLE_STD, &err_off[i]);
+}
+
+/* ---- Multi-threaded batch wrappers, used to check very large batches in
+ * seconds. The messages are cut into contiguous ranges of about equal input
+ * bytes; each thread runs the plain per-message loop above over its range.
+ * in_len == NULL selects the packed form (in_begin is then in_off). */
+typedef struct {
+    int dir;
+    const uint8_t *src;
+    const int64_t *in_begin, *in_len, *out_off;
+    int64_t begin, end;
+    uint8_t *dst;
+    const uint8_t *flags;
+    int64_t *out_len, *err_off;
+} oracle_batch_piece;
+
+static void *oracle_batch_piece_run(void *arg)
+{
+    oracle_batch_piece *w = (oracle_batch_piece *)arg;
+    const int64_t b = w->begin, k = w->end - w->begin;
+    const uint8_t *fl = w->flags ? w->flags + b : NULL;
+    if (k <= 0) return NULL;
+    if (w->in_len == NULL) {
+        if (w->dir == 0)
+            oracle_encode_batch(w->src, w->in_begin + b, k, w->dst, w->out_off + b, fl, w->out_len + b);
+        else
+            oracle_decode_batch(w->src, w->in_begin + b, k, w->dst, w->out_off + b, fl, w->out_len + b,
+                                w->err_off + b);
+    } else {
+        if (w->dir == 0)
+            oracle_encode_gather(w->src, w->in_begin + b, w->in_len + b, k, w->dst, w->out_off + b, fl,
+                                 w->out_len + b);
+        else
+            oracle_decode_gather(w->src, w->in_begin + b, w->in_len + b, k, w->dst, w->out_off + b, fl,
+                                 w->out_len + b, w->err_off + b);
+    }
+    return NULL;
+}
+
+static int64_t oracle_msg_len(const int64_t *in_begin, const int64_t *in_len, int64_t i)
+{
+    return in_len ? in_len[i] : in_begin[i + 1] - in_begin[i];
+}
+
+static void oracle_batch_pieces(int dir, const uint8_t *src, const int64_t *in_begin, const int64_t *in_len,
+                                int64_t N, uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
+                                int64_t *out_len, int64_t *err_off, int threads)
+{
+    oracle_batch_piece *w;
+    pthread_t *tid;
+    int64_t total = 0, acc = 0, i = 0;
+    if (N <= 0) return;
+    if (threads < 1) threads = 1;
+    if (threads > 1024) threads = 1024;
+    for (int64_t j = 0; j < N; j++) total += oracle_msg_len(in_begin, in_len, j);
+    w = (oracle_batch_piece *)calloc((size_t)threads, sizeof(*w));
+    tid = (pthread_t *)calloc((size_t)threads, sizeof(*tid));
+    for (int t = 0; t < threads; t++) {
+        /* this range takes messages until its share of the bytes is reached */
+        int64_t goal = (total / threads) * (t + 1);
+        w[t].dir = dir; w[t].src = src; w[t].in_begin = in_begin; w[t].in_len = in_len;
+        w[t].out_off = out_off; w[t].dst = dst; w[t].flags = flags; w[t].out_len = out_len;
+        w[t].err_off = err_off;
+        w[t].begin = i;
+        if (t == threads - 1) i = N;
+        else while (i < N && acc < goal) acc += oracle_msg_len(in_begin, in_len, i++);
+        w[t].end = i;
+        pthread_create(&tid[t], NULL, oracle_batch_piece_run, &w[t]);
+    }
+    for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    free(w);
+    free(tid);
+}
+
+void oracle_encode_batch_mt(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                            const int64_t *out_off, const uint8_t *flags, int64_t *out_len, int threads)
+{
+    oracle_batch_pieces(0, src, in_off, NULL, N, dst, out_off, flags, out_len, NULL, threads);
+}
+
+void oracle_decode_batch_mt(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                            const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                            int64_t *err_off, int threads)
+{
+    oracle_batch_pieces(1, src, in_off, NULL, N, dst, out_off, flags, out_len, err_off, threads);
+}
+
+void oracle_encode_gather_mt(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
+                             uint8_t *dst, const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                             int threads)
+{
+    oracle_batch_pieces(0, src, in_begin, in_len, N, dst, out_off, flags, out_len, NULL, threads);
+}
+
+void oracle_decode_gather_mt(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
+                             uint8_t *dst, const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                             int64_t *err_off, int threads)
+{
+    oracle_batch_pieces(1, src, in_begin, in_len, N, dst, out_off, flags, out_len, err_off, threads);
+}

@@ -448,6 +448,76 @@ def test_multithreaded_wrappers_equal_plain():
             assert oracle.decode(t2[:-1], threads=3)[:2] == (-1, t.size // 2)
 
 
+def test_multithreaded_batch_wrappers_equal_plain():
+    """The threaded batch loops split the messages into ranges; results equal
+    the one-thread loops for every thread count, including more threads than
+    messages and ranges made of one huge message."""
+    rng = np.random.default_rng(19)
+    for N, top in [(0, 10), (1, 5000), (3, 40), (257, 3000), (2000, 200)]:
+        lens = rng.integers(0, top, N)
+        if N > 2:
+            lens[N // 2] = 50_000
+        off = np.zeros(N + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        data = rng.integers(0, 256, int(off[-1]) + 1, dtype=np.uint8)
+        flags = rng.integers(0, 2, N).astype(np.uint8)
+        want = oracle.encode_batch(data, off, flags)
+        text, toff = want[0], want[1]
+        t2 = text.copy()
+        if text.size:
+            t2[rng.integers(0, text.size, 1 + N // 10)] = ord("*")
+        wd = oracle.decode_batch(t2, toff, flags)
+        for th in (2, 7, 64):
+            got = oracle.encode_batch(data, off, flags, threads=th)
+            assert all(np.array_equal(a, b) for a, b in zip(got, want)), (N, th)
+            gd = oracle.decode_batch(t2, toff, flags, threads=th)
+            assert np.array_equal(gd[2], wd[2]) and np.array_equal(gd[3], wd[3]), (N, th)
+            ok = wd[2] >= 0
+            for i in np.nonzero(ok)[0]:
+                s = wd[1][i]
+                assert np.array_equal(gd[0][s:s + wd[2][i]], wd[0][s:s + wd[2][i]])
+
+
+def test_gather_forms_equal_single_calls():
+    """Gather forms (spans in any order, overlapping, at any offset; output
+    slots anywhere): each message's result equals the one-message functions,
+    for one and several threads."""
+    rng = np.random.default_rng(23)
+    src = rng.integers(0, 256, 20_000, dtype=np.uint8)
+    N = 300
+    ln = rng.integers(0, 700, N).astype(np.int64)
+    ln[:3] = [0, 1, 2]
+    ib = rng.integers(0, src.size - 700, N).astype(np.int64)
+    fl = rng.integers(0, 2, N).astype(np.uint8)
+    cap = 4 * ((ln + 2) // 3)
+    oo = np.concatenate([[0], np.cumsum(cap[::-1] + 5)[:-1]])[::-1].astype(np.int64)  # reversed order, gaps
+    for th in (1, 4):
+        dst = np.zeros(int((oo + cap).max()) + 1, np.uint8)
+        wl = oracle.encode_gather(src, ib, ln, oo, dst, fl, threads=th)
+        for i in range(N):
+            want = oracle.encode(src[ib[i]:ib[i] + ln[i]], int(fl[i]))
+            assert wl[i] == want.size and np.array_equal(dst[oo[i]:oo[i] + want.size], want), (i, th)
+    # decode: the texts placed in one buffer, some corrupted
+    texts = [oracle.encode(src[ib[i]:ib[i] + ln[i]], int(fl[i])) for i in range(N)]
+    tb = np.concatenate(texts + [np.zeros(1, np.uint8)])
+    tl = np.array([t.size for t in texts], np.int64)
+    tbeg = np.concatenate([[0], np.cumsum(tl)[:-1]]).astype(np.int64)
+    for i in rng.choice(N, 30, replace=False):
+        if tl[i]:
+            tb[tbeg[i] + rng.integers(0, tl[i])] = ord("*")
+    perm = rng.permutation(N)
+    dcap = 3 * (tl // 4)
+    doo = np.concatenate([[0], np.cumsum(dcap[perm])[:-1]]).astype(np.int64)
+    for th in (1, 3):
+        dst = np.zeros(int(dcap.sum()) + 1, np.uint8)
+        gl, ge = oracle.decode_gather(tb, tbeg[perm], tl[perm], doo, dst, fl[perm], threads=th)
+        for k, i in enumerate(perm):
+            want = oracle.decode(tb[tbeg[i]:tbeg[i] + tl[i]], int(fl[i]))
+            assert (gl[k], ge[k]) == want[:2], (i, th)
+            if want[0] > 0:
+                assert np.array_equal(dst[doo[k]:doo[k] + want[0]], want[2])
+
+
 def test_nopad_variants():
     rng = np.random.default_rng(4)
     for n in range(0, 50):

@@ -50,12 +50,22 @@ MUTANTS = {
     "nopad_accepts_len_mod4_1": ("    if (bad < 0 && n % 4 == 1) bad = n;\n    if (bad >= 0) { *err_off = bad; return -1; }",
                                  "    if (bad >= 0) { *err_off = bad; return -1; }"),
     "nopad_tail_one_byte_short": ("for (int64_t k = 0; k < r - 1; k++) p[o++]", "for (int64_t k = 0; k < r - 2; k++) p[o++]"),
-    # batch loops
-    "batch_encode_ignores_flags": ("dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
-                                   "dst + out_off[i],\n                                   ORACLE_STD);"),
-    "batch_decode_ignores_flags": ("flags ? flags[i] : ORACLE_STD, &err_off[i]);", "ORACLE_STD, &err_off[i]);"),
+    # batch loops (packed and gather forms)
+    "batch_encode_ignores_flags": ("in_off[i + 1] - in_off[i], dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
+                                   "in_off[i + 1] - in_off[i], dst + out_off[i],\n                                   ORACLE_STD);"),
+    "batch_decode_ignores_flags": ("in_off[i + 1] - in_off[i], dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD, &err_off[i]);",
+                                   "in_off[i + 1] - in_off[i], dst + out_off[i],\n                                   ORACLE_STD, &err_off[i]);"),
     "batch_output_at_input_offset": ("in_off[i + 1] - in_off[i], dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
                                      "in_off[i + 1] - in_off[i], dst + in_off[i],\n                                   flags ? flags[i] : ORACLE_STD);"),
+    "gather_encode_ignores_flags": ("in_len[i], dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD);",
+                                    "in_len[i], dst + out_off[i],\n                                   ORACLE_STD);"),
+    "gather_decode_ignores_flags": ("in_len[i], dst + out_off[i],\n                                   flags ? flags[i] : ORACLE_STD, &err_off[i]);",
+                                    "in_len[i], dst + out_off[i],\n                                   ORACLE_STD, &err_off[i]);"),
+    "gather_encode_drops_last_byte": ("oracle_encode(src + in_begin[i], in_len[i],",
+                                      "oracle_encode(src + in_begin[i], in_len[i] - (in_len[i] > 0),"),
+    "gather_decode_at_packed_offset": ("oracle_decode(src + in_begin[i], in_len[i],",
+                                       "oracle_decode(src + in_begin[0] + i, in_len[i],"),
+    "mt_batch_range_skips_message": ("        w[t].begin = i;\n", "        w[t].begin = i + (t == 1 && i < N);\n"),
 }
 
 PIN_TESTS = [
@@ -76,6 +86,8 @@ PIN_TESTS = [
     lambda t1: pins.test_appendix_a_strict_checks(),
     lambda t1: pins.test_appendix_a_strict_accepts_exactly_the_canonical_texts(t1, oracle.STD),
     lambda t1: pins.test_nopad_variants(),
+    lambda t1: pins.test_gather_forms_equal_single_calls(),
+    lambda t1: pins.test_multithreaded_batch_wrappers_equal_plain(),
 ]
 
 

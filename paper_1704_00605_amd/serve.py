@@ -40,6 +40,7 @@ class Banks:
         # never '=': an injected '=' at the end of a request's slice could be valid padding
         vals = np.array([workloads.corruption_byte(r, 0, T - 1, T) for r in ranks], np.uint8)
         self.inject_pos = pos
+        self.inject_val = vals
         self.dec[T + torch.from_numpy(pos).to(device)] = torch.from_numpy(vals).to(device)
         torch.cuda.synchronize()
 
@@ -58,7 +59,8 @@ def build_requests(trace, banks, seed=41):
     size = trace["size"].astype(np.int64)
     C = banks.corpus.numel()
     T = banks.text_len
-    in_len = np.where(op == 0, size, 4 * ((size + 2) // 3)).astype(np.int64)
+    text_len, _ = codec.batch_slots(codec.DIR_ENCODE, size)
+    in_len = np.where(op == 0, size, text_len).astype(np.int64)
     in_begin = np.zeros(n, dtype=np.int64)
     enc = op == 0
     in_begin[enc] = (rng.uniform(size=int(enc.sum())) * (C - size[enc] + 1)).astype(np.int64)
@@ -68,8 +70,13 @@ def build_requests(trace, banks, seed=41):
     bad = np.nonzero(trace["corrupt"] & dec)[0]
     if bad.size:
         pick = banks.inject_pos[rng.integers(0, banks.inject_pos.size, bad.size)]
-        rel = np.floor(trace["corrupt_u"][bad] * in_len[bad]).astype(np.int64)
-        start = np.clip((pick - rel) // 4 * 4, 0, (T - in_len[bad]) // 4 * 4)
+        Lb = in_len[bad]
+        rel = np.floor(trace["corrupt_u"][bad] * Lb).astype(np.int64)
+        # slices start at multiples of 4: round down, unless that pushes the
+        # injected character past the end of the slice
+        start = (pick - rel) // 4 * 4
+        start = np.where(pick - start >= Lb, start + 4, start)
+        start = np.clip(start, 0, (T - Lb) // 4 * 4)
         in_begin[bad] = T + start
     return {"t_arrival": trace["t_arrival"].astype(np.float64), "op": op, "in_begin": in_begin,
             "in_len": in_len, "flags": np.zeros(n, dtype=np.uint8)}

@@ -265,56 +265,85 @@ def test_heavy_mix_scaled():
     check_decode(text, toff, flags)
 
 
-def test_heavy_mix_8192_full_size_sampled():
-    """The heavy-tailed mix at full size (8,192 messages, 7.25 GB, per-message
-    alphabets, 41 corrupted) in the autotuned launch shape, as timed: every
-    length and verdict against its closed form or the oracle, the corrupted
-    messages and a seeded sample of the others (the largest, the smallest,
-    the first and the last among them) byte for byte against the oracle one
-    by one, and every valid message's decoded bytes against its payload."""
+def _host_threads():
+    import os
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+# the launch shapes the benchmark timed on the 100,000-message batch (per-wave
+# ranges, 128 lanes x 4 units; 32,768 / 16,384 workgroups)
+UNEVEN_TIMED = {E: dict(layout=1, block=128, units_per_lane=4, grid=32768),
+                D: dict(layout=1, block=128, units_per_lane=4, grid=16384)}
+
+
+@pytest.mark.parametrize("shape", ["timed", "autotuned"])
+def test_uneven_100k_in_timed_shapes(shape):
+    """The 100,000-message batch in the launch shape the benchmark times (the
+    recorded per-wave shape, and the autotuner's pick for this device, cache
+    bypassed): every message's characters, lengths, verdicts, error offsets
+    and decoded bytes against the oracle."""
     from paper_1704_00605_amd import autotune
 
+    w = workloads.uneven()
+    data, off = w["payload"], w["in_off"]
+    if shape == "timed":
+        te, td = UNEVEN_TIMED[E], UNEVEN_TIMED[D]
+    else:
+        te, _ = autotune.tune(E, dev(data), dev(off), None, in_off_host=off, reps=1, use_cache=False)
+    check_encode(data, off, tune=te)
+    text, toff = encode_text(data, off)
+    applied = workloads.corrupt_text(text, toff, w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"])
+    assert len(applied) == 1000
+    if shape == "autotuned":
+        td, _ = autotune.tune(D, dev(text), dev(toff), None, in_off_host=toff, reps=1, use_cache=False)
+    gl, ge = check_decode(text, toff, tune=td)
+    assert (ge >= 0).sum() == 1000
+
+
+def test_heavy_mix_8192_full_size_against_oracle():
+    """The heavy-tailed mix at full size (8,192 messages, 7.25 GB, per-message
+    alphabets, 41 corrupted) in the autotuned launch shape, as timed: the
+    whole batch of characters equals the threaded oracle's batch, every
+    message's length, verdict and error offset equals the oracle's, and every
+    valid message's decoded bytes equal the oracle's decoded bytes."""
+    from paper_1704_00605_amd import autotune
+
+    th = _host_threads()
     w = workloads.heavy_mix()
     data, off, flags = w["payload"], w["in_off"], w["flags"]
     N = off.size - 1
-    lens = np.diff(off)
+    want_t, want_toff, want_tl = oracle.encode_batch(data, off, flags, threads=th)
     src, in_off, fl = dev(data), dev(off), dev(flags)
     tune_e, _ = autotune.tune(E, src, in_off, fl, in_off_host=off, reps=1, use_cache=False)
     text, toff_d, tl = codec.encode_batch(src, in_off, flags=fl, tune=tune_e)
     toff = host(toff_d)
-    assert np.array_equal(host(tl)[:N], 4 * ((lens + 2) // 3))
-    # corruptions as the benchmark applies them, on the device
+    assert np.array_equal(toff, want_toff) and np.array_equal(host(tl)[:N], want_tl)
+    assert torch.equal(text[: want_t.size], dev(want_t))
+    del src
+    # corruptions as the benchmark applies them, on the oracle's text and on
+    # the device text alike
     ids, u, rk = w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"]
     tlen = np.diff(toff)
     pos = np.minimum(np.floor(u * tlen[ids]).astype(np.int64), np.maximum(tlen[ids] - 1, 0))
     vals = np.array([workloads.corruption_byte(int(r), int(flags[i]), int(p), int(tlen[i]))
                      for r, i, p in zip(rk, ids, pos)], np.uint8)
-    # the sample: corrupted messages plus seeded others, before the text changes
-    rng = np.random.default_rng(11)
-    clean = np.setdiff1d(np.arange(N), ids)
-    pick = np.unique(np.concatenate([ids, rng.choice(clean, 40, replace=False),
-                                     [clean[np.argmax(lens[clean])], clean[np.argmin(lens[clean])], clean[0], clean[-1]]]))
-    want_t, want_toff, _ = oracle.encode_batch(np.concatenate([data[off[i]:off[i + 1]] for i in pick]),
-                                               np.concatenate([[0], np.cumsum(lens[pick])]), flags[pick])
-    for k, i in enumerate(pick):
-        got = host(text[toff[i]:toff[i] + tlen[i]])
-        assert np.array_equal(got, want_t[want_toff[k]:want_toff[k + 1]]), i
+    want_t[toff[ids] + pos] = vals
     text[dev(toff[ids] + pos)] = dev(vals)
+    wd, wdo, wl, we = oracle.decode_batch(want_t, want_toff, flags, threads=th)
+    del want_t
+    bad = np.zeros(N, bool)
+    bad[ids] = True
+    assert (we[bad] >= 0).all() and (we[~bad] == -1).all()
     tune_d, _ = autotune.tune(D, text, toff_d, fl, in_off_host=toff, reps=1, use_cache=False)
     out, oo_d, ol, er = codec.decode_batch(text, toff_d, flags=fl, tune=tune_d)
     oo, gl, ge = host(oo_d), host(ol)[:N], host(er)[:N]
-    bad = np.zeros(N, bool)
-    bad[ids] = True
-    assert np.array_equal(gl[~bad], lens[~bad]) and (ge[~bad] == -1).all()
-    sub = np.concatenate([host(text[toff[i]:toff[i + 1]]) for i in pick])
-    wd, wdo, wl, we = oracle.decode_batch(sub, np.concatenate([[0], np.cumsum(tlen[pick])]), flags[pick])
-    assert np.array_equal(gl[pick], wl) and np.array_equal(ge[pick], we)
-    for k, i in enumerate(pick):
-        if wl[k] > 0:
-            assert np.array_equal(host(out[oo[i]:oo[i] + wl[k]]), wd[wdo[k]:wdo[k] + wl[k]]), i
-    assert (we[np.isin(pick, ids)] >= 0).all()
-    for i in np.nonzero(~bad)[0]:
-        assert torch.equal(out[oo[i]:oo[i] + lens[i]], src[off[i]:off[i + 1]]), i
+    assert np.array_equal(gl, wl) and np.array_equal(ge, we)
+    del text
+    wdd = dev(wd)
+    del wd
+    for i in np.nonzero(wl > 0)[0]:
+        assert torch.equal(out[oo[i]:oo[i] + wl[i]], wdd[wdo[i]:wdo[i] + wl[i]]), i
 
 
 def test_bindings_reject_bad_arguments_before_launch():

@@ -41,8 +41,6 @@
  *         a 64-byte result slot and a pinned readback word, then reused;
  *       b64_decode_ws: per thread and device, its verdict slots (once) and
  *         a workspace grown to the largest input seen;
- *       b64_batch_out_offsets: stream-ordered partial sums (hipMallocAsync,
- *         freed on the same stream) for each call;
  *       b64_graph_create_batch: a private capture stream and the graph;
  *       b64_server_run: per-stream staging buffers, freed before it returns.
  *     The asynchronous and batched calls take caller-owned workspaces.
@@ -164,13 +162,23 @@ int64_t b64_decode_ws(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
 #define B64_DIR_ENCODE 0
 #define B64_DIR_DECODE 1
 
-/* Device exclusive scan of per-message output slots: out_off[0] = 0 and
+/* Device exclusive scan of per-message output slots (computed in place in
+ * out_off, no other memory): out_off[0] = 0 and
  * out_off[i+1] - out_off[i] = 4 * ceil(len_i / 3) (encode), or the decode
  * capacity 3 * floor(len_i / 4) (+ max(0, len_i mod 4 - 1) for an unpadded
  * message) rounded up to a multiple of 4, so that every slot keeps dst's
  * 4-byte alignment. out_off has N+1 entries. Enqueued on `stream`. */
 int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *out_off,
                           const uint8_t *flags, void *stream);
+
+/* Host form of the slot layout, for message lengths h_len[0, N) and
+ * per-message flags h_flags (nullable; both HOST arrays): h_need[i] (nullable)
+ * receives the bytes the kernels may write for message i (its encoded length
+ * in its mode, or its decode capacity), h_out_off (nullable, N+1 entries) the
+ * same exclusive scan b64_batch_out_offsets computes on the device. Pure host
+ * function; B64_BAD_ARG for a negative length. */
+int b64_batch_slots(int dir, const int64_t *h_len, const uint8_t *h_flags, int64_t N, int64_t *h_need,
+                    int64_t *h_out_off);
 
 /* Launch shape of the persistent batched kernels. A zero field means "use
  * the default". block: threads per workgroup (64..1024, multiple of 64);

@@ -78,6 +78,7 @@ SIGNATURES = {
     "b64_decode_ws": (_i64, [_p, _i64, _p, _pi64, _i32, _p]),
     "b64_set_ws_tune": (_i32, [_ptune]),
     "b64_batch_out_offsets": (_i32, [_i32, _p, _i64, _p, _p, _p]),
+    "b64_batch_slots": (_i32, [_i32, _p, _p, _i64, _p, _p]),
     "b64_batch_workspace_bytes": (_i64, [_i64]),
     "b64_encode_batch": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _i64, _ptune, _p]),
     "b64_decode_batch": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _ptune, _p]),

@@ -14,7 +14,7 @@ from ._lib import (ALPHABET_STD, ALPHABET_URL, DIR_DECODE, DIR_ENCODE, FLAG_NOPA
                    FLAG_URL, MODE_NOPAD, MODE_STRICT, B64Error, Tune, check, lib)
 
 __all__ = [
-    "encode", "decode", "decode_async", "encoded_len", "decoded_max", "batch_out_offsets",
+    "encode", "decode", "decode_async", "encoded_len", "decoded_max", "batch_out_offsets", "batch_slots",
     "encode_batch", "decode_batch", "encode_batch_gather", "decode_batch_gather", "encode_each", "decode_each",
     "workspace_bytes", "Workspace", "set_single_tune", "decode_ws", "decode_ws_async", "ws_workspace_bytes",
     "set_ws_tune",
@@ -122,7 +122,7 @@ def decode_ws(src, alphabet=ALPHABET_STD, out=None, stream=None):
     index in the coordinates of ``src``. Waits for ``stream``."""
     src = _dev_u8(src, "src")
     n = src.numel()
-    cap = 3 * (n // 4)
+    cap = decoded_max(n)
     if out is None:
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=src.device)
     else:
@@ -145,7 +145,7 @@ def decode_ws_async(src, out, result, workspace, alphabet=ALPHABET_STD, stream=N
     _dev_u8(out, "out")
     _dev_u8(workspace, "workspace")
     n = src.numel()
-    if out.numel() < 3 * (n // 4):
+    if out.numel() < decoded_max(n):
         raise ValueError("out is too small")
     if workspace.numel() < ws_workspace_bytes(n):
         raise ValueError("workspace is too small")
@@ -328,14 +328,33 @@ def _validate_packed(src, in_off, out_off, dst, direction, flags=None):
     _check_slots(oo[: lens.size], lens, direction, flags, dst)
 
 
+def batch_slots(direction, lens, flags=None):
+    """Host form of the batch slot layout (``b64_batch_slots``): for message
+    lengths ``lens`` and per-message flags (host arrays), returns (need,
+    out_off): the bytes the kernels may write per message and the N+1 slot
+    offsets that ``b64_batch_out_offsets`` computes on the device."""
+    import numpy as np
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    N = lens.size
+    if fl is not None and fl.size < N:
+        raise ValueError(f"flags needs one byte per message ({N})")
+    need = np.empty(max(N, 1), np.int64)
+    oo = np.empty(N + 1, np.int64)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    check(lib().b64_batch_slots(int(direction), P(lens) if N else None, None if fl is None else P(fl), N,
+                                P(need), P(oo)), "b64_batch_slots")
+    return need[:N], oo
+
+
+def _host_flags(flags):
+    return None if flags is None else flags.cpu().numpy()
+
+
 def _check_slots(oo, lens, direction, flags, dst):
     import numpy as np
-    fl = np.zeros(lens.size, np.uint8) if flags is None else flags.cpu().numpy()
-    if direction == DIR_ENCODE:
-        cap = 4 * ((lens + 2) // 3)
-    else:
-        cap = 3 * (lens // 4) + np.where(fl & FLAG_NOPAD, np.maximum(lens % 4 - 1, 0), 0)
-    if lens.size and (np.any(oo < 0) or np.any(oo + cap > dst.numel())):
+    need, _ = batch_slots(direction, lens, _host_flags(flags))
+    if lens.size and (np.any(oo < 0) or np.any(oo + need > dst.numel())):
         raise ValueError("output slots fall outside dst")
 
 
@@ -349,20 +368,10 @@ def _validate_gather(src, in_begin, in_len, out_off, dst, direction, flags=None)
 
 
 def _gather_out_off(in_len, direction, flags, device):
-    """Output slots laid out like b64_batch_out_offsets (decode slots rounded
-    up to a multiple of 4)."""
-    import numpy as np
-    n = in_len.cpu().numpy()
-    fl = np.zeros(n.size, np.uint8) if flags is None else flags.cpu().numpy()
-    if direction == DIR_ENCODE:
-        cap = 4 * ((n + 2) // 3)
-    else:
-        cap = 3 * (n // 4) + np.where(fl & FLAG_NOPAD, np.maximum(n % 4 - 1, 0), 0)
-        cap = (cap + 3) // 4 * 4
-    oo = np.zeros(n.size, np.int64)
-    if n.size > 1:
-        oo[1:] = np.cumsum(cap)[:-1]
-    return torch.from_numpy(oo).to(device), int(cap.sum())
+    """Output slots laid out as b64_batch_out_offsets lays them out, computed
+    by the library on the host from the lengths."""
+    _, oo = batch_slots(direction, in_len.cpu().numpy(), _host_flags(flags))
+    return torch.from_numpy(oo[:-1].copy()).to(device), int(oo[-1])
 
 
 def encode_batch_gather(src, in_begin, in_len, out_off=None, flags=None, dst=None, out_len=None,

@@ -32,12 +32,12 @@ __device__ __forceinline__ int64_t units_of(int dir, int64_t len)
     return dir == B64_DIR_ENCODE ? (len + 11) / 12 : (len + 15) / 16;
 }
 
-__device__ __forceinline__ int64_t enc_len_of(int64_t len, int nopad)
+__host__ __device__ __forceinline__ int64_t enc_len_of(int64_t len, int nopad)
 {
     return nopad ? 4 * (len / 3) + ((len % 3) ? (len % 3) + 1 : 0) : 4 * ((len + 2) / 3);
 }
 
-__device__ __forceinline__ int64_t dec_cap_of(int64_t len, int nopad)
+__host__ __device__ __forceinline__ int64_t dec_cap_of(int64_t len, int nopad)
 {
     return 3 * (len / 4) + ((nopad && (len & 3) >= 2) ? (len & 3) - 1 : 0);
 }
@@ -45,7 +45,7 @@ __device__ __forceinline__ int64_t dec_cap_of(int64_t len, int nopad)
 // Decode output slot of the batch layout: the capacity rounded up to a
 // multiple of 4 so every slot starts where dst's alignment allows dword
 // stores (each 16-character unit writes 12 bytes at offset 12j of its slot).
-__device__ __forceinline__ int64_t dec_slot_of(int64_t len, int nopad)
+__host__ __device__ __forceinline__ int64_t dec_slot_of(int64_t len, int nopad)
 {
     return (dec_cap_of(len, nopad) + 3) & ~(int64_t)3;
 }
@@ -646,29 +646,57 @@ __device__ __forceinline__ int64_t out_size_of(int dir, Msgs msgs, const uint8_t
     return dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
 }
 
-// Per-chunk totals of output sizes (chunks of PLAN_CHUNK messages).
+// The output-offset scan runs in place in out_off, with no other memory:
+// chunk c (PLAN_CHUNK messages) first stores its total at the index where the
+// next chunk starts (or at N), a one-block pass turns those entries into
+// their inclusive prefix (which is already the final out_off there), and
+// every chunk then fills the rest of its range from the entry at its start.
+__device__ __forceinline__ int64_t chunk_end(int64_t c, int64_t N)
+{
+    return std::min<int64_t>((c + 1) * PLAN_CHUNK, N);
+}
+
+// out_off[chunk_end(c)] = total output size of chunk c.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_out_reduce(int dir, Msgs msgs, int64_t N,
                                                           const uint8_t *__restrict__ flags,
-                                                          int64_t *__restrict__ partial)
+                                                          int64_t *__restrict__ out_off)
 {
     const int64_t i0 = (int64_t)blockIdx.x * PLAN_CHUNK + threadIdx.x * PLAN_PER_THREAD;
     int64_t s = 0;
     for (int k = 0; k < PLAN_PER_THREAD; k++)
         if (i0 + k < N) s += out_size_of(dir, msgs, flags, i0 + k);
     s = block_sum(s);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) out_off[chunk_end(blockIdx.x, N)] = s;
 }
 
-// out_off = exclusive scan of output sizes (N + 1 entries).
+// One block: inclusive scan of the chunk totals, in place.
+__global__ __launch_bounds__(1024) void k_out_top(int64_t N, int64_t chunks, int64_t *__restrict__ out_off)
+{
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < chunks; base += blockDim.x) {
+        const int64_t c = base + threadIdx.x;
+        const int64_t v = c < chunks ? out_off[chunk_end(c, N)] : 0;
+        const int64_t ex = block_exclusive_scan(v);
+        const int64_t carry = s_carry;
+        if (c < chunks) out_off[chunk_end(c, N)] = carry + ex + v;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) s_carry = carry + ex + v;
+        __syncthreads();
+    }
+    if (N == 0 && threadIdx.x == 0) out_off[0] = 0;
+}
+
+// out_off[i] for the messages of chunk c, from the final entry at the chunk's
+// start (0 for the first chunk); the entry at the chunk's end is already final.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_out_scan(int dir, Msgs msgs, int64_t N,
                                                         const uint8_t *__restrict__ flags,
-                                                        const int64_t *__restrict__ partial,
                                                         int64_t *__restrict__ out_off)
 {
-    int64_t pre = 0;
-    for (int64_t c = threadIdx.x; c < blockIdx.x; c += blockDim.x) pre += partial[c];
-    pre = block_sum(pre);
-    const int64_t i0 = (int64_t)blockIdx.x * PLAN_CHUNK + threadIdx.x * PLAN_PER_THREAD;
+    const int64_t c0 = (int64_t)blockIdx.x * PLAN_CHUNK;
+    const int64_t pre = blockIdx.x == 0 ? 0 : out_off[c0];
+    const int64_t i0 = c0 + threadIdx.x * PLAN_PER_THREAD;
     int64_t v[PLAN_PER_THREAD];
     int64_t s = 0;
     for (int k = 0; k < PLAN_PER_THREAD; k++) {
@@ -678,11 +706,9 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_out_scan(int dir, Msgs msgs, int
     int64_t ex = pre + block_exclusive_scan(s);
     for (int k = 0; k < PLAN_PER_THREAD; k++) {
         const int64_t i = i0 + k;
-        if (i < N) out_off[i] = ex;
-        if (i == N - 1) out_off[N] = ex + v[k];
+        if (i < N && (i != c0 || blockIdx.x == 0)) out_off[i] = ex;
         ex += v[k];
     }
-    if (N == 0 && blockIdx.x == 0 && threadIdx.x == 0) out_off[0] = 0;
 }
 
 // ================================================================= host ==
@@ -703,19 +729,31 @@ int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *ou
     hipStream_t s = (hipStream_t)stream;
     const Msgs msgs{in_off, nullptr};
     const int64_t chunks = std::max<int64_t>(1, (N + PLAN_CHUNK - 1) / PLAN_CHUNK);
-    // partial sums in stream-ordered memory, so calls on several streams
-    // never share it
-    int64_t *partial = nullptr;
-    HIP_TRY(hipMallocAsync((void **)&partial, 8 * chunks, s));
-    hipLaunchKernelGGL(k_out_reduce, (unsigned)chunks, PLAN_BLOCK, 0, s, dir, msgs, N, flags, partial);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_out_scan, (unsigned)chunks, PLAN_BLOCK, 0, s, dir, msgs, N, flags,
-                           (const int64_t *)partial, out_off);
-        e = hipGetLastError();
+    if (chunks > (int64_t)1 << 31) return b64i_fail(B64_BAD_ARG, "too many messages");
+    hipLaunchKernelGGL(k_out_reduce, (unsigned)chunks, PLAN_BLOCK, 0, s, dir, msgs, N, flags, out_off);
+    LAUNCH_TRY();
+    hipLaunchKernelGGL(k_out_top, 1, 1024, 0, s, N, chunks, out_off);
+    LAUNCH_TRY();
+    hipLaunchKernelGGL(k_out_scan, (unsigned)chunks, PLAN_BLOCK, 0, s, dir, msgs, N, flags, out_off);
+    LAUNCH_TRY();
+    return B64_OK;
+}
+
+int b64_batch_slots(int dir, const int64_t *h_len, const uint8_t *h_flags, int64_t N, int64_t *h_need,
+                    int64_t *h_out_off)
+{
+    if (dir != B64_DIR_ENCODE && dir != B64_DIR_DECODE) return b64i_fail(B64_BAD_ARG, "bad direction");
+    if (N < 0 || (N > 0 && !h_len)) return b64i_fail(B64_BAD_ARG, "bad lengths");
+    int64_t acc = 0;
+    for (int64_t i = 0; i < N; i++) {
+        const int64_t len = h_len[i];
+        if (len < 0) return b64i_fail(B64_BAD_ARG, "negative length of message %lld", (long long)i);
+        const int nopad = h_flags ? (h_flags[i] & M_NOPAD) : 0;
+        if (h_need) h_need[i] = dir == B64_DIR_ENCODE ? enc_len_of(len, nopad) : dec_cap_of(len, nopad);
+        if (h_out_off) h_out_off[i] = acc;
+        acc += dir == B64_DIR_ENCODE ? 4 * ((len + 2) / 3) : dec_slot_of(len, nopad);
     }
-    HIP_TRY(hipFreeAsync(partial, s));
-    if (e != hipSuccess) return b64i_fail(B64_HIP_ERROR, "kernel launch failed: %s", hipGetErrorString(e));
+    if (h_out_off) h_out_off[N] = acc;
     return B64_OK;
 }
 

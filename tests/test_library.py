@@ -89,3 +89,28 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(_lib.B64Error):
         _lib.lib()
+
+
+def test_batch_slots_host_layout(L):
+    """b64_batch_slots against the length law written out: encoded lengths
+    (padded and unpadded), decode capacities rounded to 4-byte slots."""
+    import numpy as np
+    from paper_1704_00605_amd import codec
+
+    rng = np.random.default_rng(3)
+    lens = np.concatenate([np.arange(0, 70), rng.integers(0, 1 << 40, 50)]).astype(np.int64)
+    flags = rng.integers(0, 8, lens.size).astype(np.uint8)
+    nopad = (flags & _lib.FLAG_NOPAD) != 0
+    need, oo = codec.batch_slots(_lib.DIR_ENCODE, lens, flags)
+    enc_pad = 4 * ((lens + 2) // 3)
+    enc_nopad = 4 * (lens // 3) + np.where(lens % 3, lens % 3 + 1, 0)
+    assert np.array_equal(need, np.where(nopad, enc_nopad, enc_pad))
+    assert oo[0] == 0 and np.array_equal(np.diff(oo), enc_pad)
+    need, oo = codec.batch_slots(_lib.DIR_DECODE, lens, flags)
+    cap = 3 * (lens // 4) + np.where(nopad & (lens % 4 >= 2), lens % 4 - 1, 0)
+    assert np.array_equal(need, cap)
+    assert np.array_equal(np.diff(oo), (cap + 3) // 4 * 4)
+    need, oo = codec.batch_slots(_lib.DIR_DECODE, np.zeros(0, np.int64))
+    assert need.size == 0 and oo.tolist() == [0]
+    with pytest.raises(_lib.B64Error):
+        codec.batch_slots(_lib.DIR_ENCODE, np.array([5, -1], np.int64))

@@ -397,9 +397,13 @@ def test_plain_entry_points_on_the_null_stream():
     bd = dev(bad)
     r = L.b64_decode(ctypes.c_void_p(bd.data_ptr()), m, ctypes.c_void_p(out.data_ptr()), ctypes.byref(err))
     assert (r, err.value) == (_lib.INVALID_INPUT, pos) == oracle.decode(bad)[:2]
-    # length error: 4k + 3 characters of valid symbols -> -1 at n
+    # length error: 4k + 3 symbols (the padded final quad cut off) -> -1 at n
+    k = m - 5
+    r = L.b64_decode(ctypes.c_void_p(td.data_ptr()), k, ctypes.c_void_p(out.data_ptr()), ctypes.byref(err))
+    assert (r, err.value) == oracle.decode(want_t[:k])[:2] == (-1, k)
+    # ... and cut inside the padding: the '=' left at index m - 2 is then invalid
     r = L.b64_decode(ctypes.c_void_p(td.data_ptr()), m - 1, ctypes.c_void_p(out.data_ptr()), ctypes.byref(err))
-    assert (r, err.value) == oracle.decode(want_t[: m - 1])[:2] == (-1, m - 1)
+    assert (r, err.value) == oracle.decode(want_t[: m - 1])[:2] == (-1, m - 2)
 
 
 def test_device_slot_scan_equals_host_layout():

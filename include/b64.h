@@ -43,7 +43,8 @@
  *         a workspace grown to the largest input seen;
  *       b64_graph_create_batch: a private capture stream and the graph;
  *       b64_server_run: per-stream staging buffers, freed before it returns.
- *     The asynchronous and batched calls take caller-owned workspaces.
+ *     The asynchronous and batched calls take caller-owned workspaces;
+ *     b64_decode_batch_noalloc uses a static device array instead.
  */
 #ifndef B64HIP_H
 #define B64HIP_H
@@ -220,6 +221,23 @@ int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8
                      const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
                      int64_t *err_off, void *workspace, int64_t workspace_bytes,
                      const b64_tune *tune, void *stream);
+
+/* Largest batch b64_decode_batch_noalloc accepts. */
+#define B64_NOALLOC_MAX_MESSAGES (1 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * b64_decode_batch without a workspace argument. Its planning workspace is a
+ * static device array of the library (about 8 MiB, held by every device the
+ * library runs on until the process ends), so the call allocates nothing and
+ * needs no workspace; it only enqueues kernels on `stream`. N is at most
+ * B64_NOALLOC_MAX_MESSAGES (B64_BAD_ARG beyond, before any work). All calls
+ * on one device share that array: calls whose GPU work overlaps on one device
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Everything else, results included, as b64_decode_batch. */
+int b64_decode_batch_noalloc(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                             const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                             int64_t *err_off, const b64_tune *tune, void *stream);
 
 /* Gather forms: message i is src[in_begin[i], in_begin[i] + in_len[i]) with
  * in_begin / in_len DEVICE arrays of N entries (messages may overlap, be in

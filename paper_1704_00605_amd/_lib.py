@@ -28,6 +28,8 @@ FLAG_NOPAD = 0x04
 DIR_ENCODE = 0
 DIR_DECODE = 1
 
+NOALLOC_MAX_MESSAGES = 1 << 20
+
 
 class Tune(ctypes.Structure):
     """``b64_tune``: launch shape of the persistent batched kernels."""
@@ -82,6 +84,7 @@ SIGNATURES = {
     "b64_batch_workspace_bytes": (_i64, [_i64]),
     "b64_encode_batch": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _i64, _ptune, _p]),
     "b64_decode_batch": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _i64, _ptune, _p]),
+    "b64_decode_batch_noalloc": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _ptune, _p]),
     "b64_encode_each": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p]),
     "b64_decode_each": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p]),
     "b64_set_single_tune": (_i32, [_i32, _ptune]),

@@ -11,11 +11,11 @@ import torch
 
 from . import _lib
 from ._lib import (ALPHABET_STD, ALPHABET_URL, DIR_DECODE, DIR_ENCODE, FLAG_NOPAD, FLAG_STRICT,
-                   FLAG_URL, MODE_NOPAD, MODE_STRICT, B64Error, Tune, check, lib)
+                   FLAG_URL, MODE_NOPAD, MODE_STRICT, NOALLOC_MAX_MESSAGES, B64Error, Tune, check, lib)
 
 __all__ = [
     "encode", "decode", "decode_async", "encoded_len", "decoded_max", "batch_out_offsets", "batch_slots",
-    "encode_batch", "decode_batch", "encode_batch_gather", "decode_batch_gather", "encode_each", "decode_each",
+    "encode_batch", "decode_batch", "decode_batch_noalloc", "encode_batch_gather", "decode_batch_gather", "encode_each", "decode_each",
     "workspace_bytes", "Workspace", "set_single_tune", "decode_ws", "decode_ws_async", "ws_workspace_bytes",
     "set_ws_tune",
     "ALPHABET_STD", "ALPHABET_URL", "MODE_STRICT", "MODE_NOPAD", "FLAG_URL", "FLAG_STRICT",
@@ -314,6 +314,28 @@ def decode_batch(src, in_off, out_off=None, flags=None, dst=None, out_len=None, 
                                _stream(stream))
     check(r, "b64_decode_batch")
     return dst, out_off, out_len[:N], err_off[:N]
+
+
+def decode_batch_noalloc(src, in_off, out_off, dst, out_len, err_off, flags=None, tune=None, stream=None,
+                         validate=True):
+    """``b64_decode_batch_noalloc``: decode_batch with every buffer supplied by
+    the caller and the planning workspace taken from the library's static
+    device array (no allocation; at most NOALLOC_MAX_MESSAGES messages; calls
+    overlapping on one device race). Returns ``(out_len, err_off)`` views."""
+    src = _dev_u8(src, "src")
+    in_off = _i64_dev(in_off, "in_off")
+    N = in_off.numel() - 1
+    flags = _flags_dev(flags, N)
+    _i64_slots(out_off, N, "out_off")
+    _i64_slots(out_len, N, "out_len")
+    _i64_slots(err_off, N, "err_off")
+    _dev_u8(dst, "dst")
+    if validate:
+        _validate_packed(src, in_off, out_off, dst, DIR_DECODE, flags)
+    r = lib().b64_decode_batch_noalloc(_ptr(src), _ptr(in_off), N, _ptr(dst), _ptr(out_off), _ptr(flags),
+                                       _ptr(out_len), _ptr(err_off), _tune(tune), _stream(stream))
+    check(r, "b64_decode_batch_noalloc")
+    return out_len[:N], err_off[:N]
 
 
 def _validate_packed(src, in_off, out_off, dst, direction, flags=None):

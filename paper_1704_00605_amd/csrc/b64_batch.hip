@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "b64.h"
@@ -712,13 +713,19 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_out_scan(int dir, Msgs msgs, int
 }
 
 // ================================================================= host ==
+// Planning workspace of a batch of N messages: unit_off (N + 1 entries) and
+// one partial sum per chunk of PLAN_CHUNK messages.
+constexpr int64_t batch_ws_bytes(int64_t N)
+{
+    return 8 * (N + 1) + 8 * (N > 0 ? (N + PLAN_CHUNK - 1) / PLAN_CHUNK : 1);
+}
+
 extern "C" {
 
 int64_t b64_batch_workspace_bytes(int64_t N)
 {
     if (N < 0) return b64i_fail(B64_BAD_ARG, "negative N");
-    const int64_t chunks = (N + PLAN_CHUNK - 1) / PLAN_CHUNK;
-    return 8 * (N + 1) + 8 * std::max<int64_t>(chunks, 1);
+    return batch_ws_bytes(N);
 }
 
 int b64_batch_out_offsets(int dir, const int64_t *in_off, int64_t N, int64_t *out_off,
@@ -912,6 +919,58 @@ int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8
 {
     return decode_batch_any(src, Msgs{in_off, nullptr}, N, dst, out_off, flags, out_len, err_off,
                             workspace, workspace_bytes, tune, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// Device scratch of b64_decode_batch_noalloc: the planning workspace of up to
+// B64_NOALLOC_MAX_MESSAGES messages. Every device the library runs on holds
+// its own copy until the process ends. In host code `scratch` names a host
+// stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, once per device.
+constexpr int64_t SCRATCH_BYTES = (batch_ws_bytes(B64_NOALLOC_MAX_MESSAGES) + 255) / 256 * 256;
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device: device address of `scratch`
+
+int scratch_address(void **out)
+{
+    int dev;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return b64i_fail(B64_HIP_ERROR, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return B64_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int b64_decode_batch_noalloc(const uint8_t *src, const int64_t *in_off, int64_t N, uint8_t *dst,
+                             const int64_t *out_off, const uint8_t *flags, int64_t *out_len,
+                             int64_t *err_off, const b64_tune *tune, void *stream)
+{
+    if (N < 0) return b64i_fail(B64_BAD_ARG, "negative N");
+    if (N > B64_NOALLOC_MAX_MESSAGES)
+        return b64i_fail(B64_BAD_ARG, "b64_decode_batch_noalloc takes at most %d messages (got %lld)",
+                         B64_NOALLOC_MAX_MESSAGES, (long long)N);
+    if (N == 0) return B64_OK;
+    void *ws;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return decode_batch_any(src, Msgs{in_off, nullptr}, N, dst, out_off, flags, out_len, err_off, ws,
+                            SCRATCH_BYTES, tune, (hipStream_t)stream);
 }
 
 int b64_encode_batch_gather(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len,

@@ -182,16 +182,27 @@ int b64_batch_slots(int dir, const int64_t *h_len, const uint8_t *h_flags, int64
                     int64_t *h_out_off);
 
 /* Launch shape of the persistent batched kernels. A zero field means "use
- * the default". block: threads per workgroup (64..1024, multiple of 64);
- * units_per_lane: 12-byte (encode) / 16-character (decode) units each lane
- * carries per step (1, 2, 4 or 8); grid: workgroups of the persistent launch
- * (0 = 32 per compute unit for layout 0, 8 for layout 1); layout: how the
- * flattened units of all messages are shared out -
+ * the default". block: threads per workgroup (64..1024, multiple of 64;
+ * layout 2 runs 256); units_per_lane: 12-byte (encode) / 16-character
+ * (decode) units each lane carries per step (1, 2, 4 or 8); grid: workgroups
+ * of the launch (0 = 32 per compute unit for layouts 0 and 2, 8 for layout
+ * 1); layout: how the flattened units of all messages are shared out -
  *   0  tiles of block * units_per_lane units, grid-stride over the batch
  *      (blocks in flight cover one dense window; a tile inside one message
  *      runs the single-buffer step) - best when large messages dominate;
  *   1  one contiguous range of 64-unit groups per wave, walked with a
- *      message cursor - best for many small and mid-size messages.
+ *      message cursor - best for many small and mid-size messages in gather
+ *      batches;
+ *   2  staged tiles of 256 * units_per_lane units, one workgroup each
+ *      (grid-stride when grid is smaller than the tile count, which a caller
+ *      that knows the lengths can pass exactly): the planning pass records
+ *      where each tile's input starts, the workgroup reads the tile's input
+ *      as aligned 16-byte chunks straight into LDS and each lane takes its
+ *      unit from there at any alignment - best for many small and mid-size
+ *      messages in packed batches. Packed batches only: gather batches with
+ *      layout 2 run layout 1. Tiles past the first N + 4096 (more than the
+ *      tile table holds) or starting more than 256 messages run a slower
+ *      per-lane path.
  * The autotuner picks all four per device and message-size histogram. */
 typedef struct b64_tune {
     int32_t block;
@@ -200,7 +211,8 @@ typedef struct b64_tune {
     int32_t layout;
 } b64_tune;
 
-/* Device workspace (bytes) the batched calls need for N messages. */
+/* Device workspace (bytes) the batched calls need for N messages: about
+ * 24 N + 64 KiB (unit offsets, partial sums, and layout 2's tile table). */
 int64_t b64_batch_workspace_bytes(int64_t N);
 
 /* Encode N messages in one persistent launch (after a device planning pass
@@ -228,7 +240,7 @@ int b64_decode_batch(const uint8_t *src, const int64_t *in_off, int64_t N, uint8
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation):
  * b64_decode_batch without a workspace argument. Its planning workspace is a
- * static device array of the library (about 8 MiB, held by every device the
+ * static device array of the library (about 24 MiB, held by every device the
  * library runs on until the process ends), so the call allocates nothing and
  * needs no workspace; it only enqueues kernels on `stream`. N is at most
  * B64_NOALLOC_MAX_MESSAGES (B64_BAD_ARG beyond, before any work). All calls

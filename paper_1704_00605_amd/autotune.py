@@ -1,8 +1,10 @@
 """Autotuner for the persistent batched kernels.
 
-Searches the work layout (grid-stride tiles, or one contiguous range of
-64-unit groups per wave) and the launch shape (threads per workgroup, units
-per lane, workgroups in the persistent grid) of ``b64_encode_batch`` /
+Searches the work layout (grid-stride tiles, one contiguous range of 64-unit
+groups per wave, or staged tiles whose input goes through LDS) and the launch
+shape (threads per workgroup, units per lane, workgroups in the grid; for the
+staged layout also one workgroup per tile, counted on the host from the
+message lengths) of ``b64_encode_batch`` /
 ``b64_decode_batch`` on the actual batch, timing each candidate with HIP events, and caches the winner in
 a JSON file keyed by architecture, compute-unit count, direction and a coarse signature
 of the batch (message count, total bytes and the log2 histogram of message
@@ -80,9 +82,30 @@ def save_cache(c):
     os.replace(tmp, p)
 
 
-def candidates(cus):
-    return [dict(block=b, units_per_lane=u, grid=g * cus, layout=lay)
-            for lay, (blocks, units, grids) in SPACE.items() for b in blocks for u in units for g in grids]
+# staged layout (2): 256-thread workgroups, units per lane, and either one
+# workgroup per tile (counted from the batch's lengths on the host) or a
+# grid of 32 workgroups per CU walking the tiles
+STAGED_UNITS = (1, 2, 4, 8)
+
+
+def staged_tiles(direction, in_off_host, units_per_lane):
+    """Tiles of the staged layout for a packed batch (known on the host)."""
+    unit = 12 if direction == codec.DIR_ENCODE else 16
+    lens = np.diff(np.asarray(in_off_host, dtype=np.int64))
+    U = int((-(-lens // unit)).sum())
+    T = 256 * units_per_lane
+    return max(1, -(-U // T))
+
+
+def candidates(cus, direction=None, in_off_host=None):
+    out = [dict(block=b, units_per_lane=u, grid=g * cus, layout=lay)
+           for lay, (blocks, units, grids) in SPACE.items() for b in blocks for u in units for g in grids]
+    for u in STAGED_UNITS:
+        grids = {32 * cus}
+        if in_off_host is not None and direction is not None:
+            grids.add(min(staged_tiles(direction, in_off_host, u), 1 << 20))
+        out += [dict(block=256, units_per_lane=u, grid=g, layout=2) for g in sorted(grids)]
+    return out
 
 
 def time_call(fn, reps):
@@ -118,7 +141,7 @@ def tune(direction, src, in_off, flags=None, in_off_host=None, reps=3, cands=Non
     ws = codec.Workspace()
     results = []
     t0 = time.perf_counter()
-    for c in cands or candidates(cus):
+    for c in cands or candidates(cus, direction, in_off_host):
         if direction == codec.DIR_ENCODE:
             fn = lambda: codec.encode_batch(src, in_off, out_off, flags, dst, out_len, tune=c, workspace=ws,
                                             validate=False)

@@ -8,6 +8,11 @@
 //                                 grid-stride.
 //   k_enc_batch_w / k_dec_batch_w persistent codec, wave layout: one
 //                                 contiguous range of 64-unit groups per wave.
+//   k_batch_s                     staged layout: one workgroup per tile of
+//                                 units, the tile's input read as aligned
+//                                 16-byte chunks into LDS, its messages found
+//                                 from a tile table filled by the planning
+//                                 pass.
 //   k_dec_batch_final             per-message verdicts.
 //   k_out_reduce / k_out_scan     exclusive scan of output sizes.
 #include <hip/hip_runtime.h>
@@ -110,14 +115,25 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_reduce(Msgs msgs, int64_t N
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Tile table of the staged layout (tiles of T consecutive units of the
+// flattened unit space): m[t] is the message holding tile t's first unit
+// (t < W) and A[t] the input byte where that unit starts (t <= W). T == 0:
+// no table. Packed batches only (a tile's input is then one byte range,
+// [A[t], A[t + 1]), or up to in_off[N] for the last tile).
+struct TileTab {
+    int64_t T, W;
+    int64_t *A, *m;
+};
+
 // unit_off = exclusive scan of units per message (N + 1 entries), plus
 // per-message initialisation: encode out_len (known from the length);
-// decode out_len = 0 and err_off = ERR_NONE (the atomicMin sentinel).
+// decode out_len = 0 and err_off = ERR_NONE (the atomicMin sentinel); and
+// the tile table entries of the tiles whose first unit lies in the message.
 template <int DIR>
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
     Msgs msgs, int64_t N, const uint8_t *__restrict__ flags,
     const int64_t *__restrict__ partial, int64_t *__restrict__ unit_off,
-    int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
+    int64_t *__restrict__ out_len, int64_t *__restrict__ err_off, TileTab tt)
 {
     int64_t pre = 0;
     for (int64_t c = threadIdx.x; c < blockIdx.x; c += blockDim.x) pre += partial[c];
@@ -144,7 +160,18 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
     int64_t ex = pre + block_exclusive_scan(s);
     for (int k = 0; k < PLAN_PER_THREAD; k++) {
         const int64_t i = i0 + k;
-        if (i < N) unit_off[i] = ex;
+        if (i < N) {
+            unit_off[i] = ex;
+            if (tt.T > 0 && u[k] > 0) {
+                // tiles t with t * T in [ex, ex + u[k])
+                const int64_t ub = DIR == B64_DIR_ENCODE ? 12 : 16, b = msgs.b(i);
+                const int64_t te = min((ex + u[k] + tt.T - 1) / tt.T, tt.W + 1);
+                for (int64_t t = (ex + tt.T - 1) / tt.T; t < te; t++) {
+                    tt.A[t] = b + ub * (t * tt.T - ex);
+                    if (t < tt.W) tt.m[t] = i;
+                }
+            }
+        }
         if (i == N - 1) unit_off[N] = ex + u[k];
         ex += u[k];
     }
@@ -628,6 +655,204 @@ __global__ __launch_bounds__(1024) void k_dec_batch_t(
     batch_tiles<UPL>(a, fast, general, true);
 }
 
+// ---------------------------------------------------------------- layout 2
+// Staged layout: one workgroup per tile of S_BLOCK * UPL consecutive units
+// (grid-stride when the grid is smaller than the tile count). A packed
+// batch's units tile its input without gaps, so a tile's input is the byte
+// range [A[t], A[t + 1]) of the tile table whatever the message boundaries
+// and alignments inside it. The workgroup reads that range as aligned 16-byte
+// chunks (each holds a byte of the range, so every read lies on a page the
+// buffer occupies) into LDS, in the same round as the metadata of the
+// messages from the tile's first one on; each lane then finds its unit's
+// message by a binary search over the staged message starts and reads its
+// 12 (encode) or 16 (decode) bytes from LDS at any alignment. Tiles past the
+// table or starting more than S_META messages take the per-lane path of the
+// tile layout instead.
+constexpr int S_BLOCK = 256;
+constexpr int S_META = 256;
+
+__device__ __forceinline__ int64_t tile_cap(int64_t N) { return N + 4096; }
+
+// Bytes o .. o + 15 of an LDS byte buffer (any o with o + 20 inside it).
+__device__ __forceinline__ void lds_read16(const uint32_t *lds, uint32_t o, uint32_t (&w)[4])
+{
+    const uint32_t d = o >> 2, sh = o & 3;
+    uint32_t x[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) x[k] = lds[d + k];
+#pragma unroll
+    for (int k = 0; k < 4; k++) w[k] = alignb(x[k + 1], x[k], sh);
+}
+
+// Zeroes bytes r .. 15 of w (r in 1..16).
+__device__ __forceinline__ void keep_bytes(uint32_t (&w)[4], int r)
+{
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int keep = r - 4 * k;
+        w[k] = keep >= 4 ? w[k] : keep <= 0 ? 0u : (w[k] & ((1u << (8 * keep)) - 1u));
+    }
+}
+
+// Largest m in [lo, N) with unit_off[m] <= u (unit_off[lo] <= u < unit_off[N]),
+// by one lane on its own.
+__device__ __forceinline__ int64_t lane_search_msg(const int64_t *__restrict__ unit_off, int64_t N, int64_t u,
+                                                   int64_t lo)
+{
+    int64_t hi = N;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (unit_off[mid] <= u) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int DIR, int UPL>
+__global__ __launch_bounds__(S_BLOCK) void k_batch_s(
+    const uint8_t *__restrict__ src, const int64_t *__restrict__ in_off, int64_t N,
+    uint8_t *__restrict__ dst, const int64_t *__restrict__ out_off,
+    const uint8_t *__restrict__ flags, const int64_t *__restrict__ unit_off,
+    const int64_t *__restrict__ tile_A, const int64_t *__restrict__ tile_m, int64_t W,
+    int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
+{
+    constexpr bool ENC = DIR == B64_DIR_ENCODE;
+    constexpr int UB = ENC ? 12 : 16;                   // input bytes per unit
+    constexpr int64_t T = (int64_t)S_BLOCK * UPL;      // units per tile
+    constexpr int CH = (int)((T * UB + 15) / 16 + 3);  // 16-byte chunks staged (+ misalignment, + read slack)
+    constexpr int PER = (CH + S_BLOCK - 1) / S_BLOCK;
+    __shared__ uint32_t s_tab[ENC ? 32 : 128];
+    __shared__ uint4 s_data[CH];
+    __shared__ int64_t s_u[S_META + 1], s_b[S_META + 1], s_o[S_META];
+    __shared__ uint8_t s_f[S_META];
+    __shared__ int s_over;
+    lds_fill(s_tab, ENC ? &c_tab.enc[0][0] : &c_tab.dec[0][0], ENC ? 128 : 512);
+    const int tid = threadIdx.x;
+    const int64_t U = unit_off[N];
+    const int64_t ntiles = (U + T - 1) / T;
+    const uint8_t *tabs = (const uint8_t *)s_tab;
+    const uint32_t *lds = (const uint32_t *)s_data;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        __syncthreads();  // the previous tile's LDS reads (and the table fill) are done
+        const int64_t t0 = t * T, t1 = min(t0 + T, U);
+        int64_t m0;
+        uintptr_t c0 = 0;
+        int K = 0;
+        bool staged = t < W;
+        if (staged) {
+            m0 = tile_m[t];
+            const int64_t A = tile_A[t];
+            const int64_t B = t + 1 < ntiles ? tile_A[t + 1] : in_off[N];
+            // one round of loads: the messages from m0 on (one per thread,
+            // plus one more by thread 0) and the tile's input chunks
+            const int64_t idx = m0 + tid;
+            const int64_t mu = idx <= N ? unit_off[idx] : INT64_MAX;
+            const int64_t mb = idx <= N ? in_off[idx] : 0;
+            const int64_t mo = idx < N ? out_off[idx] : 0;
+            const int mf = (idx < N && flags) ? flags[idx] : 0;
+            int64_t mu_x = INT64_MAX, mb_x = 0;
+            if (tid == 0 && m0 + S_META <= N) {
+                mu_x = unit_off[m0 + S_META];
+                mb_x = in_off[m0 + S_META];
+            }
+            c0 = ((uintptr_t)src + (uintptr_t)A) >> 4;
+            const int64_t nch = B > A ? (int64_t)((((uintptr_t)src + (uintptr_t)B - 1) >> 4) - c0) + 1 : 0;
+            // chunks straight into LDS (no registers): lane l of wave w loads
+            // chunk k * S_BLOCK + 64 w + l, which the load writes at 16 l past
+            // its wave's LDS base
+            const int wv = tid >> 6;
+#pragma unroll
+            for (int k = 0; k < PER; k++) {
+                const int64_t i = tid + k * S_BLOCK;
+                if (i < nch) {
+                    const uint8_t *p = src + (int64_t)((((uintptr_t)c0 + i) << 4) - (uintptr_t)src);
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)p, (__attribute__((address_space(3))) void *)(s_data + k * S_BLOCK + 64 * wv), 16, 0, 0);
+                }
+            }
+            s_u[tid] = mu;
+            s_b[tid] = mb;
+            s_o[tid] = mo;
+            s_f[tid] = (uint8_t)mf;
+            if (tid == 0) {
+                s_u[S_META] = mu_x;
+                s_b[S_META] = mb_x;
+                s_over = mu_x < t1;
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's chunks have landed in LDS
+            // messages starting before t1 (a prefix, unit_off does not
+            // decrease); also the barrier for the LDS writes above
+            K = __syncthreads_count(mu < t1);
+            staged = !s_over;
+        } else {
+            m0 = block_find_msg(unit_off, N, t0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < UPL; k++) {
+            const int64_t u = t0 + (int64_t)k * S_BLOCK + tid;
+            if (u >= t1) break;
+            // the unit's message (index mi), its place j in it, and its bytes
+            int64_t mi, j, b, n, o;
+            int fl;
+            uint32_t w[4];
+            if (staged) {
+                int lo = 0, hi = K;  // largest r < K with s_u[r] <= u
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_u[mid] <= u) lo = mid;
+                    else hi = mid;
+                }
+                mi = m0 + lo;
+                j = u - s_u[lo];
+                b = s_b[lo];
+                n = s_b[lo + 1] - b;
+                o = s_o[lo];
+                fl = s_f[lo];
+                lds_read16(lds, (uint32_t)((uintptr_t)src + (uintptr_t)(b + UB * j) - (c0 << 4)), w);
+            } else {  // rare: tiles past the table or starting over S_META messages
+                mi = lane_search_msg(unit_off, N, u, m0);
+                j = u - unit_off[mi];
+                b = in_off[mi];
+                n = in_off[mi + 1] - b;
+                o = out_off[mi];
+                fl = flags ? flags[mi] : 0;
+                load_upto16(src + b + UB * j, (int)min(n - UB * j, (int64_t)UB), w);
+            }
+            if (ENC) {
+                const uint8_t *tab = tabs + 64 * (fl & M_URL);
+                uint8_t *q = dst + o + 16 * j;
+                if (12 * j + 12 <= n) {
+                    uint32_t oc[4];
+                    enc_unit(w[0], w[1], w[2], tab, oc[0], oc[1], oc[2], oc[3]);
+                    store_words<4, true>(q, oc);
+                } else {
+                    const int r = (int)(n - 12 * j);
+                    keep_bytes(w, r);
+                    enc_tail_fast(w, r, q, tab, fl & M_NOPAD);
+                }
+            } else {
+                const uint8_t *tab = tabs + 256 * (fl & M_URL);
+                uint8_t *q = dst + o + 12 * j;
+                if (16 * j + 16 < n) {
+                    uint32_t oc[3];
+                    const uint32_t bad = dec_unit(w[0], w[1], w[2], w[3], tab, oc[0], oc[1], oc[2]);
+                    store_words<3, true>(q, oc);
+                    if (bad & INVALID) {
+                        const int64_t pos = 16 * j + dec_first_bad(w[0], w[1], w[2], w[3], tab);
+                        atomicMin((unsigned long long *)&err_off[mi], (unsigned long long)pos);
+                    }
+                } else {
+                    const int res = dec_tail_fast(w, (int)(n - 16 * j), n, q, tab, fl);
+                    if (res >= 0)
+                        atomicMin((unsigned long long *)&err_off[mi], (unsigned long long)(16 * j + res));
+                    else
+                        out_len[mi] = 12 * j + (-1 - res);
+                }
+            }
+        }
+    }
+}
+
 __global__ void k_dec_batch_final(int64_t N, int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
@@ -713,11 +938,14 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_out_scan(int dir, Msgs msgs, int
 }
 
 // ================================================================= host ==
-// Planning workspace of a batch of N messages: unit_off (N + 1 entries) and
-// one partial sum per chunk of PLAN_CHUNK messages.
+// Planning workspace of a batch of N messages: unit_off (N + 1 entries), one
+// partial sum per chunk of PLAN_CHUNK messages, and the staged layout's tile
+// table (A: W + 1 entries, m: W entries, W = N + 4096).
+constexpr int64_t plan_chunks(int64_t N) { return N > 0 ? (N + PLAN_CHUNK - 1) / PLAN_CHUNK : 1; }
+constexpr int64_t tile_cap_h(int64_t N) { return N + 4096; }
 constexpr int64_t batch_ws_bytes(int64_t N)
 {
-    return 8 * (N + 1) + 8 * (N > 0 ? (N + PLAN_CHUNK - 1) / PLAN_CHUNK : 1);
+    return 8 * (N + 1) + 8 * plan_chunks(N) + 8 * (2 * tile_cap_h(N) + 1);
 }
 
 extern "C" {
@@ -780,29 +1008,51 @@ int batch_shape(const b64_tune *t, int *block, int *upl, int *grid, int *layout)
     const bool tiles = *layout == 0;
     *block = (t && t->block) ? t->block : (tiles ? 512 : 256);
     *upl = (t && t->units_per_lane) ? t->units_per_lane : 2;
-    *grid = (t && t->grid) ? t->grid : cus * (tiles ? 32 : 8);
-    if (*layout != 0 && *layout != 1) return b64i_fail(B64_BAD_ARG, "bad layout %d", *layout);
+    *grid = (t && t->grid) ? t->grid : cus * (*layout == 1 ? 8 : 32);
+    if (*layout < 0 || *layout > 2) return b64i_fail(B64_BAD_ARG, "bad layout %d", *layout);
+    if (*layout == 2 && *block != S_BLOCK)
+        return b64i_fail(B64_BAD_ARG, "the staged layout runs %d-thread workgroups (block %d)", S_BLOCK, *block);
     if (*block < 64 || *block > 1024 || (*block & 63)) return b64i_fail(B64_BAD_ARG, "bad block size %d", *block);
     if (*upl != 1 && *upl != 2 && *upl != 4 && *upl != 8) return b64i_fail(B64_BAD_ARG, "bad units_per_lane %d", *upl);
     if (*grid < 1 || *grid > (1 << 20)) return b64i_fail(B64_BAD_ARG, "bad grid %d", *grid);
     return B64_OK;
 }
 
+// Device planning pass; fills the staged layout's tile table when the
+// launch shape asks for that layout on a packed batch (tt->T > 0 then).
 template <int DIR>
 int plan(Msgs msgs, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes, int64_t *out_len,
-         int64_t *err_off, int64_t **unit_off, hipStream_t s)
+         int64_t *err_off, int64_t **unit_off, const b64_tune *tune, TileTab *tt, hipStream_t s)
 {
     if (ws_bytes < b64_batch_workspace_bytes(N) || !ws) return b64i_fail(B64_BAD_ARG, "workspace too small");
-    const int64_t chunks = std::max<int64_t>(1, (N + PLAN_CHUNK - 1) / PLAN_CHUNK);
+    int block, upl, grid, layout;
+    int rc = batch_shape(tune, &block, &upl, &grid, &layout);
+    if (rc) return rc;
+    const int64_t chunks = plan_chunks(N);
     *unit_off = (int64_t *)ws;
     int64_t *partial = (int64_t *)ws + (N + 1);
+    *tt = TileTab{0, 0, nullptr, nullptr};
+    if (layout == 2 && msgs.len == nullptr) {
+        tt->T = (int64_t)S_BLOCK * upl;
+        tt->W = tile_cap_h(N);
+        tt->A = partial + chunks;
+        tt->m = tt->A + tt->W + 1;
+    }
     hipLaunchKernelGGL((k_plan_reduce<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, msgs, N, partial);
     LAUNCH_TRY();
     hipLaunchKernelGGL((k_plan_scan<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, msgs, N, flags, partial,
-                       *unit_off, out_len, err_off);
+                       *unit_off, out_len, err_off, *tt);
     LAUNCH_TRY();
     return B64_OK;
 }
+
+#define B64_LAUNCH_STAGED(DIRV, UPL, ...)                                                        \
+    switch (UPL) {                                                                               \
+    case 1: hipLaunchKernelGGL((k_batch_s<DIRV, 1>), grid, S_BLOCK, 0, s, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((k_batch_s<DIRV, 4>), grid, S_BLOCK, 0, s, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL((k_batch_s<DIRV, 8>), grid, S_BLOCK, 0, s, __VA_ARGS__); break;   \
+    default: hipLaunchKernelGGL((k_batch_s<DIRV, 2>), grid, S_BLOCK, 0, s, __VA_ARGS__); break;  \
+    }
 
 #define B64_LAUNCH_UPL(KERN, UPL, ...)                                                   \
     switch (UPL) {                                                                       \
@@ -813,12 +1063,20 @@ int plan(Msgs msgs, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes,
     }
 
 int launch_enc_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
-                     const uint8_t *flags, const int64_t *unit_off, const b64_tune *tune, hipStream_t s)
+                     const uint8_t *flags, const int64_t *unit_off, const b64_tune *tune, const TileTab &tt,
+                     hipStream_t s)
 {
     int block, upl, grid, layout;
     int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
-    if (layout == 1) {
+    if (layout == 2 && tt.T == 0) {  // no tile table (gather form): per-wave ranges instead
+        layout = 1;
+        upl = std::min(upl, 4);
+    }
+    if (layout == 2) {
+        B64_LAUNCH_STAGED(B64_DIR_ENCODE, upl, src, msgs.begin, N, dst, out_off, flags, unit_off, tt.A, tt.m,
+                          tt.W, nullptr, nullptr);
+    } else if (layout == 1) {
         B64_LAUNCH_UPL(k_enc_batch_w, upl, src, msgs, N, dst, out_off, flags, unit_off);
     } else {
         B64_LAUNCH_UPL(k_enc_batch_t, upl, src, msgs, N, dst, out_off, flags, unit_off);
@@ -829,12 +1087,19 @@ int launch_enc_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
 
 int launch_dec_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
                      const uint8_t *flags, const int64_t *unit_off, int64_t *out_len, int64_t *err_off,
-                     const b64_tune *tune, hipStream_t s)
+                     const b64_tune *tune, const TileTab &tt, hipStream_t s)
 {
     int block, upl, grid, layout;
     int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
-    if (layout == 1) {
+    if (layout == 2 && tt.T == 0) {  // no tile table (gather form): per-wave ranges instead
+        layout = 1;
+        upl = std::min(upl, 4);
+    }
+    if (layout == 2) {
+        B64_LAUNCH_STAGED(B64_DIR_DECODE, upl, src, msgs.begin, N, dst, out_off, flags, unit_off, tt.A, tt.m,
+                          tt.W, out_len, err_off);
+    } else if (layout == 1) {
         B64_LAUNCH_UPL(k_dec_batch_w, upl, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off);
     } else {
         B64_LAUNCH_UPL(k_dec_batch_t, upl, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off);
@@ -857,9 +1122,10 @@ int encode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
     int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
     int64_t *unit_off;
-    rc = plan<B64_DIR_ENCODE>(msgs, N, flags, ws, ws_bytes, out_len, nullptr, &unit_off, s);
+    TileTab tt;
+    rc = plan<B64_DIR_ENCODE>(msgs, N, flags, ws, ws_bytes, out_len, nullptr, &unit_off, tune, &tt, s);
     if (rc) return rc;
-    return launch_enc_batch(src, msgs, N, dst, out_off, flags, unit_off, tune, s);
+    return launch_enc_batch(src, msgs, N, dst, out_off, flags, unit_off, tune, tt, s);
 }
 
 int decode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, const int64_t *out_off,
@@ -873,9 +1139,10 @@ int decode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
     int rc = batch_shape(tune, &block, &upl, &grid, &layout);
     if (rc) return rc;
     int64_t *unit_off;
-    rc = plan<B64_DIR_DECODE>(msgs, N, flags, ws, ws_bytes, out_len, err_off, &unit_off, s);
+    TileTab tt;
+    rc = plan<B64_DIR_DECODE>(msgs, N, flags, ws, ws_bytes, out_len, err_off, &unit_off, tune, &tt, s);
     if (rc) return rc;
-    return launch_dec_batch(src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off, tune, s);
+    return launch_dec_batch(src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off, tune, tt, s);
 }
 
 }  // namespace
@@ -889,7 +1156,7 @@ int b64i_encode_planned(const uint8_t *src, const int64_t *in_begin, const int64
                         const int64_t *unit_off, const b64_tune *tune, hipStream_t s)
 {
     if (N <= 0) return B64_OK;
-    return launch_enc_batch(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, unit_off, tune, s);
+    return launch_enc_batch(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, unit_off, tune, TileTab{}, s);
 }
 
 int b64i_decode_planned(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
@@ -899,7 +1166,7 @@ int b64i_decode_planned(const uint8_t *src, const int64_t *in_begin, const int64
 {
     if (N <= 0) return B64_OK;
     return launch_dec_batch(src, Msgs{in_begin, in_len}, N, dst, out_off, flags, unit_off, out_len,
-                            err_off, tune, s);
+                            err_off, tune, TileTab{}, s);
 }
 
 extern "C" {

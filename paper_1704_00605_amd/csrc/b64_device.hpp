@@ -136,15 +136,13 @@ __device__ __forceinline__ void store_upto16(uint8_t *q, const uint32_t (&o)[4],
     }
 }
 
-// Final partial unit of a message: r bytes (1..12) at s. Writes the
-// characters of Algorithm 1 (including its tail: one leftover byte -> two
-// characters, two -> three, then '=' padding unless nopad) to q and returns
-// their number.
-__device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
-                                     const uint8_t *tab, int nopad)
+// Final partial unit of a message: r bytes (1..12) held little-endian in w
+// (zero beyond r). Writes the characters of Algorithm 1 (including its tail:
+// one leftover byte -> two characters, two -> three, then '=' padding unless
+// nopad) to q and returns their number.
+__device__ __forceinline__ int enc_tail_w(const uint32_t (&w)[4], int r, uint8_t *__restrict__ q,
+                                          const uint8_t *tab, int nopad)
 {
-    uint32_t w[4];
-    load_upto16(s, r, w);
     uint32_t o[4] = {0u, 0u, 0u, 0u};
     int c = 0;
 #pragma unroll
@@ -164,6 +162,47 @@ __device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8
             }
         }
         c += emit;
+    }
+    store_upto16(q, o, c);
+    return c;
+}
+
+// The same for r bytes (1..12) at s in global memory.
+__device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
+                                     const uint8_t *tab, int nopad)
+{
+    uint32_t w[4];
+    load_upto16(s, r, w);
+    return enc_tail_w(w, r, q, tab, nopad);
+}
+
+// The same for bytes already in registers (out of line: called once per
+// message).
+__device__ __noinline__ int enc_tail_r(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int r,
+                                       uint8_t *__restrict__ q, const uint8_t *tab, int nopad)
+{
+    const uint32_t w[4] = {w0, w1, w2, w3};
+    return enc_tail_w(w, r, q, tab, nopad);
+}
+
+// Final partial unit of a message through the full-unit routine: r bytes
+// (1..11) in w, zero beyond r, so the characters of the last group's missing
+// bits come out as those of zero bits; then the positions Algorithm 1 pads
+// become '=' (or are not written, unpadded). Returns the characters written.
+__device__ __forceinline__ int enc_tail_fast(const uint32_t (&w)[4], int r, uint8_t *__restrict__ q,
+                                             const uint8_t *tab, int nopad)
+{
+    uint32_t o[4];
+    enc_unit(w[0], w[1], w[2], tab, o[0], o[1], o[2], o[3]);
+    const int g = r / 3, rem = r - 3 * g;  // full groups, leftover bytes of the last one
+    int c = 4 * g;
+    if (rem) {
+        // group g fills dword g: its first rem + 1 characters are real
+        const uint32_t keep = (1u << (8 * (rem + 1))) - 1u;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (k == g) o[k] = (o[k] & keep) | (0x3d3d3d3du & ~keep);
+        c += nopad ? rem + 1 : 4;
     }
     store_upto16(q, o, c);
     return c;
@@ -209,22 +248,18 @@ __device__ __noinline__ int dec_first_bad(uint32_t w0, uint32_t w1, uint32_t w2,
     return 16;
 }
 
-// Final unit of a message of n characters: r characters (1..16) at c, which
-// are characters n-r .. n-1. Applies the padding rules ('=' only as the last
-// one or two characters of a length divisible by 4; unpadded mode: '='
-// invalid, n mod 4 == 1 is a length error), the optional strict leftover-bit
-// check (Appendix A), and writes the decoded bytes to q. Returns the first
-// offending index relative to c (r stands for "length error at n"), or -1;
-// *nout receives the number of bytes written (0 when an error was found).
-// The characters are loaded once into registers. Inline form: the batched
-// decode finishes many messages per wave, where a call costs more than the
-// extra code (dec_tail below is the out-of-line form for once-per-launch use).
-__device__ __forceinline__ int dec_tail_inl(const uint8_t *__restrict__ c, int r, int64_t n,
-                                            uint8_t *__restrict__ q, const uint8_t *tab, int mode,
-                                            int *nout)
+// Final unit of a message of n characters: r characters (1..16), which are
+// characters n-r .. n-1, held little-endian in w (zero beyond r). Applies the
+// padding rules ('=' only as the last one or two characters of a length
+// divisible by 4; unpadded mode: '=' invalid, n mod 4 == 1 is a length
+// error), the optional strict leftover-bit check (Appendix A), and writes the
+// decoded bytes to q. Returns the first offending index relative to the
+// unit's start (r stands for "length error at n"), or -1; *nout receives the
+// number of bytes written (0 when an error was found).
+__device__ __forceinline__ int dec_tail_w(const uint32_t (&w)[4], int r, int64_t n,
+                                          uint8_t *__restrict__ q, const uint8_t *tab, int mode,
+                                          int *nout)
 {
-    uint32_t w[4];
-    load_upto16(c, r, w);
     const bool nopad = (mode & M_NOPAD) != 0;
     int pads = 0;
     if (!nopad && (n & 3) == 0 && byte_of(w, r - 1) == '=') {
@@ -274,11 +309,68 @@ __device__ __forceinline__ int dec_tail_inl(const uint8_t *__restrict__ c, int r
     return -1;
 }
 
+// dec_tail_w through the full-unit routine: the characters from the padding
+// on (and past r) are read as 'A' (value 0), so one dec_unit gives the bytes
+// of every group, the first non-symbol among the rest is the first offending
+// index, and only the counts differ from an interior unit. Returns the first
+// offending index (relative to the unit, r for a length error at n), or
+// -1 - (bytes written) on success.
+__device__ __forceinline__ int dec_tail_fast(const uint32_t (&w)[4], int r, int64_t n, uint8_t *__restrict__ q,
+                                             const uint8_t *tab, int mode)
+{
+    const bool nopad = (mode & M_NOPAD) != 0;
+    int pads = 0;
+    if (!nopad && (n & 3) == 0 && byte_of(w, r - 1) == '=') pads = (r >= 2 && byte_of(w, r - 2) == '=') ? 2 : 1;
+    const int keep = r - pads;  // characters decoded as written
+    uint32_t x[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int kb = keep - 4 * k;
+        const uint32_t m = kb >= 4 ? 0xffffffffu : kb <= 0 ? 0u : (1u << (8 * kb)) - 1u;
+        x[k] = (w[k] & m) | (0x41414141u & ~m);
+    }
+    uint32_t o[4];
+    o[3] = 0;
+    const uint32_t bad = dec_unit(x[0], x[1], x[2], x[3], tab, o[0], o[1], o[2]);
+    if (bad & INVALID) return dec_first_bad(x[0], x[1], x[2], x[3], tab);
+    if (nopad ? ((n & 3) == 1) : ((n & 3) != 0)) return r;
+    // Appendix A (strict): leftover bits of a padded final quad must be zero.
+    if ((mode & M_STRICT) && pads == 2 && (tab[byte_of(w, r - 3)] & 15) != 0) return r - 3;
+    if ((mode & M_STRICT) && pads == 1 && (tab[byte_of(w, r - 2)] & 3) != 0) return r - 2;
+    const int nout = 3 * (r >> 2) - pads + ((nopad && (r & 3) >= 2) ? (r & 3) - 1 : 0);
+    store_upto16(q, o, nout);
+    return -1 - nout;
+}
+
+// The same for r characters at c in global memory, loaded once into
+// registers. Inline form: the batched decode finishes many messages per wave,
+// where a call costs more than the extra code (dec_tail below is the
+// out-of-line form for once-per-launch use).
+__device__ __forceinline__ int dec_tail_inl(const uint8_t *__restrict__ c, int r, int64_t n,
+                                            uint8_t *__restrict__ q, const uint8_t *tab, int mode,
+                                            int *nout)
+{
+    uint32_t w[4];
+    load_upto16(c, r, w);
+    return dec_tail_w(w, r, n, q, tab, mode, nout);
+}
+
 __device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64_t n,
                                      uint8_t *__restrict__ q, const uint8_t *tab, int mode,
                                      int *nout)
 {
     return dec_tail_inl(c, r, n, q, tab, mode, nout);
+}
+
+// Out-of-line form for characters already in registers. Returns the first
+// offending index (>= 0), or -1 - (bytes written) on success.
+__device__ __noinline__ int dec_tail_r(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int r, int64_t n,
+                                       uint8_t *__restrict__ q, const uint8_t *tab, int mode)
+{
+    const uint32_t w[4] = {w0, w1, w2, w3};
+    int nout;
+    const int idx = dec_tail_w(w, r, n, q, tab, mode, &nout);
+    return idx >= 0 ? idx : -1 - nout;
 }
 
 // -------------------------------------------- register and pair maps --

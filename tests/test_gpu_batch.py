@@ -97,7 +97,7 @@ def test_encode_batch_shapes(lens):
     check_encode(data, off)
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 2])
 def test_encode_batch_random_mix_with_alphabets(layout):
     rng = np.random.default_rng(1)
     for trial in range(6):
@@ -106,6 +106,78 @@ def test_encode_batch_random_mix_with_alphabets(layout):
         data, off = packed(lens, trial)
         flags = rng.integers(0, 2, N).astype(np.uint8)
         check_encode(data, off, flags, tune=dict(layout=layout))
+
+
+STAGED_SHAPES = [dict(layout=2, units_per_lane=u, grid=g) for u in (1, 2, 4, 8) for g in (0, 3, 1 << 16)]
+
+
+@pytest.mark.parametrize("tune", STAGED_SHAPES, ids=lambda t: f"upl{t['units_per_lane']}-grid{t['grid']}")
+def test_staged_layout_shapes(tune):
+    """The staged layout (tiles of 256 x units_per_lane units, input through
+    LDS) at every units-per-lane value, with a grid of 3 workgroups (many
+    tiles per workgroup), the default and one workgroup per tile: a mix of
+    empty, tiny and long messages at every start alignment (in_off[0] = 5),
+    per-message alphabets and padding modes, some decodes corrupted."""
+    rng = np.random.default_rng(31 + tune["units_per_lane"])
+    N = 1500
+    lens = np.where(rng.uniform(size=N) < 0.04, rng.integers(3000, 60_000, N), rng.integers(0, 90, N))
+    lens[rng.choice(N, 100, replace=False)] = 0
+    data, off = packed(lens, 31, base=5)
+    flags = rng.choice([0, 1, 4, 5], N).astype(np.uint8)  # std/url x padded/unpadded
+    texts = [oracle.encode_nopad(data[off[i]:off[i + 1]], flags[i] & 1) if flags[i] & 4
+             else oracle.encode(data[off[i]:off[i + 1]], flags[i] & 1) for i in range(N)]
+    dst, out_off, out_len = codec.encode_batch(dev(data), dev(off), flags=dev(flags), tune=tune)
+    d, oo, ol = host(dst), host(out_off), host(out_len)
+    for i in range(N):
+        assert ol[i] == texts[i].size and np.array_equal(d[oo[i]:oo[i] + ol[i]], texts[i]), (i, tune)
+    for i in rng.choice(N, 60, replace=False):
+        if texts[i].size:
+            texts[i] = texts[i].copy()
+            texts[i][rng.integers(0, texts[i].size)] = workloads.corruption_byte(
+                int(rng.integers(0, 192)), int(flags[i] & 1), 0, texts[i].size)
+    tl = np.array([t.size for t in texts], np.int64)
+    toff = np.zeros(N + 1, np.int64)
+    np.cumsum(tl, out=toff[1:])
+    text = np.concatenate(texts)
+    dflags = np.where(flags & 4, flags, flags | 2).astype(np.uint8)  # strict on the padded ones
+    dst, out_off, out_len, err = codec.decode_batch(dev(text), dev(toff), flags=dev(dflags), tune=tune)
+    d, oo, ol, oe = host(dst), host(out_off), host(out_len), host(err)
+    for i in range(N):
+        t = texts[i]
+        w = oracle.decode_nopad(t, dflags[i] & 1) if dflags[i] & 4 else oracle.decode_strict(t, dflags[i] & 1)
+        assert (ol[i], oe[i]) == w[:2], (i, tune)
+        if w[0] > 0:
+            assert np.array_equal(d[oo[i]:oo[i] + w[0]], w[2]), (i, tune)
+
+
+def test_staged_layout_dense_tiles_and_long_message():
+    """Tiles that start more than 256 messages (1-byte messages: the per-lane
+    path), and one 60 MB message whose tiles outnumber the tile table (N +
+    4096 entries) at 256 units per tile (the searched path), in both
+    directions, against the oracle."""
+    for lens in ([1] * 5000 + [7] * 3000, [60_000_000], [0, 3] * 2000 + [50_000_000, 5]):
+        data, off = packed(lens, len(lens))
+        for upl in (1, 4):
+            tune = dict(layout=2, units_per_lane=upl, grid=0)
+            check_encode(data, off, tune=tune)
+            text, toff = encode_text(data, off)
+            text[toff[-2] + (toff[-1] - toff[-2]) // 2] = ord("*")
+            check_decode(text, toff, tune=tune)
+
+
+def test_staged_layout_falls_back_for_gather():
+    """Gather batches have no single input range per tile: the staged layout
+    falls back to per-wave ranges and still matches the oracle."""
+    rng = np.random.default_rng(8)
+    src = rng.integers(0, 256, 300_000, dtype=np.uint8)
+    N = 400
+    ln = rng.integers(0, 3000, N).astype(np.int64)
+    ib = rng.integers(0, src.size - 3000, N).astype(np.int64)
+    dst, oo, ol = codec.encode_batch_gather(dev(src), dev(ib), dev(ln), tune=dict(layout=2, units_per_lane=4))
+    d, oo = host(dst), host(oo)
+    for i in range(N):
+        want = oracle.encode(src[ib[i]:ib[i] + ln[i]])
+        assert np.array_equal(d[oo[i]:oo[i] + want.size], want), i
 
 
 def test_encode_batch_unaligned_starts():
@@ -128,7 +200,7 @@ def test_batch_launch_shapes_agree(shape, layout):
     check_decode(text, toff, tune=tune)
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 2])
 def test_decode_batch_valid_and_corrupted(layout):
     rng = np.random.default_rng(2)
     for trial in range(5):
@@ -164,7 +236,7 @@ def test_decode_batch_garbage_lengths_and_padding():
     toff = np.zeros(lens.size + 1, dtype=np.int64)
     np.cumsum(lens, out=toff[1:])
     text = np.concatenate(msgs)
-    for layout in (0, 1):
+    for layout in (0, 1, 2):
         check_decode(text, toff, tune=dict(layout=layout))
         check_decode(text, toff, np.ones(lens.size, np.uint8), tune=dict(layout=layout))
 
@@ -254,15 +326,16 @@ def test_uneven_100k_messages():
         assert ge[m_id] >= 0 and ge[m_id] <= pos
 
 
-def test_heavy_mix_scaled():
+@pytest.mark.parametrize("tune", [None, dict(layout=2, units_per_lane=4, grid=0)])
+def test_heavy_mix_scaled(tune):
     """The heavy-tailed mix with per-message alphabets at reduced count
     (large messages 1-4 MiB) so the oracle finishes in seconds."""
     w = workloads.heavy_mix(count=1024, n_large=102, large=(1 << 20, 4 << 20), seed=3)
     data, off, flags = w["payload"], w["in_off"], w["flags"]
-    check_encode(data, off, flags)
+    check_encode(data, off, flags, tune=tune)
     text, toff = encode_text(data, off, flags)
     workloads.corrupt_text(text, toff, w["corrupt_ids"], w["corrupt_u"], w["corrupt_rank"], flags)
-    check_decode(text, toff, flags)
+    check_decode(text, toff, flags, tune=tune)
 
 
 def _host_threads():
@@ -277,7 +350,7 @@ UNEVEN_TIMED = {E: dict(layout=1, block=128, units_per_lane=4, grid=32768),
                 D: dict(layout=1, block=128, units_per_lane=4, grid=16384)}
 
 
-@pytest.mark.parametrize("shape", ["timed", "autotuned"])
+@pytest.mark.parametrize("shape", ["timed", "autotuned", "staged"])
 def test_uneven_100k_in_timed_shapes(shape):
     """The 100,000-message batch in the launch shape the benchmark times (the
     recorded per-wave shape, and the autotuner's pick for this device, cache
@@ -289,6 +362,8 @@ def test_uneven_100k_in_timed_shapes(shape):
     data, off = w["payload"], w["in_off"]
     if shape == "timed":
         te, td = UNEVEN_TIMED[E], UNEVEN_TIMED[D]
+    elif shape == "staged":
+        te = td = dict(layout=2, units_per_lane=4, grid=0)
     else:
         te, _ = autotune.tune(E, dev(data), dev(off), None, in_off_host=off, reps=1, use_cache=False)
     check_encode(data, off, tune=te)

@@ -303,12 +303,11 @@ __device__ __forceinline__ void dec_batch_unit(const uint8_t *__restrict__ src, 
             atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)pos);
         }
     } else {
-        int nout;
-        const int idx = dec_tail_inl(src + r.b + 16 * r.j, (int)(r.n - 16 * r.j), r.n, q, tab, r.fl, &nout);
-        if (idx >= 0)
-            atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)(16 * r.j + idx));
+        const int res = dec_tail_inl(src + r.b + 16 * r.j, (int)(r.n - 16 * r.j), r.n, q, tab, r.fl);
+        if (res >= 0)
+            atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)(16 * r.j + res));
         else
-            out_len[r.mm] = 12 * r.j + nout;
+            out_len[r.mm] = 12 * r.j + (-1 - res);
     }
 }
 

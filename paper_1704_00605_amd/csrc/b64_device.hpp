@@ -136,55 +136,6 @@ __device__ __forceinline__ void store_upto16(uint8_t *q, const uint32_t (&o)[4],
     }
 }
 
-// Final partial unit of a message: r bytes (1..12) held little-endian in w
-// (zero beyond r). Writes the characters of Algorithm 1 (including its tail:
-// one leftover byte -> two characters, two -> three, then '=' padding unless
-// nopad) to q and returns their number.
-__device__ __forceinline__ int enc_tail_w(const uint32_t (&w)[4], int r, uint8_t *__restrict__ q,
-                                          const uint8_t *tab, int nopad)
-{
-    uint32_t o[4] = {0u, 0u, 0u, 0u};
-    int c = 0;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int left = r - 3 * i;  // bytes from this group on
-        if (left <= 0) break;
-        const uint32_t v = (byte_of(w, 3 * i) << 16) | (byte_of(w, 3 * i + 1) << 8) | byte_of(w, 3 * i + 2);
-        uint32_t ch[4] = {tab[v >> 18], tab[(v >> 12) & 63], left >= 2 ? tab[(v >> 6) & 63] : (uint32_t)'=',
-                          left >= 3 ? tab[v & 63] : (uint32_t)'='};
-        const int emit = nopad ? (left >= 3 ? 4 : left + 1) : 4;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            if (j < emit) {
-                const int at = c + j;  // at < 16
-                const uint32_t sh = 8 * (at & 3), bits = ch[j] << sh;
-                if (at < 4) o[0] |= bits; else if (at < 8) o[1] |= bits; else if (at < 12) o[2] |= bits; else o[3] |= bits;
-            }
-        }
-        c += emit;
-    }
-    store_upto16(q, o, c);
-    return c;
-}
-
-// The same for r bytes (1..12) at s in global memory.
-__device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
-                                     const uint8_t *tab, int nopad)
-{
-    uint32_t w[4];
-    load_upto16(s, r, w);
-    return enc_tail_w(w, r, q, tab, nopad);
-}
-
-// The same for bytes already in registers (out of line: called once per
-// message).
-__device__ __noinline__ int enc_tail_r(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int r,
-                                       uint8_t *__restrict__ q, const uint8_t *tab, int nopad)
-{
-    const uint32_t w[4] = {w0, w1, w2, w3};
-    return enc_tail_w(w, r, q, tab, nopad);
-}
-
 // Final partial unit of a message through the full-unit routine: r bytes
 // (1..11) in w, zero beyond r, so the characters of the last group's missing
 // bits come out as those of zero bits; then the positions Algorithm 1 pads
@@ -206,6 +157,16 @@ __device__ __forceinline__ int enc_tail_fast(const uint32_t (&w)[4], int r, uint
     }
     store_upto16(q, o, c);
     return c;
+}
+
+// The same for the r bytes (0..11) at s in global memory (out of line: once
+// per message or per launch).
+__device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
+                                     const uint8_t *tab, int nopad)
+{
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (r > 0) load_upto16(s, r, w);
+    return enc_tail_fast(w, r, q, tab, nopad);
 }
 
 // ------------------------------------------------------ decode (a7,a9) --
@@ -240,81 +201,25 @@ __device__ __forceinline__ uint32_t dec_unit(uint32_t w0, uint32_t w1, uint32_t 
 __device__ __noinline__ int dec_first_bad(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
                                           const uint8_t *tab)
 {
-    uint32_t w[4] = {w0, w1, w2, w3};
-    for (int k = 0; k < 16; k++) {
-        uint32_t ch = (w[k >> 2] >> (8 * (k & 3))) & 0xff;
-        if (tab[ch] & INVALID) return k;
+    int first = 16;
+#pragma unroll
+    for (int k = 15; k >= 0; k--) {  // unrolled: each word picked by a constant index
+        const uint32_t x = k < 4 ? w0 : k < 8 ? w1 : k < 12 ? w2 : w3;
+        if (tab[(x >> (8 * (k & 3))) & 0xff] & INVALID) first = k;
     }
-    return 16;
+    return first;
 }
 
 // Final unit of a message of n characters: r characters (1..16), which are
-// characters n-r .. n-1, held little-endian in w (zero beyond r). Applies the
-// padding rules ('=' only as the last one or two characters of a length
-// divisible by 4; unpadded mode: '=' invalid, n mod 4 == 1 is a length
-// error), the optional strict leftover-bit check (Appendix A), and writes the
-// decoded bytes to q. Returns the first offending index relative to the
-// unit's start (r stands for "length error at n"), or -1; *nout receives the
-// number of bytes written (0 when an error was found).
-__device__ __forceinline__ int dec_tail_w(const uint32_t (&w)[4], int r, int64_t n,
-                                          uint8_t *__restrict__ q, const uint8_t *tab, int mode,
-                                          int *nout)
-{
-    const bool nopad = (mode & M_NOPAD) != 0;
-    int pads = 0;
-    if (!nopad && (n & 3) == 0 && byte_of(w, r - 1) == '=') {
-        pads = 1;
-        if (r >= 2 && byte_of(w, r - 2) == '=') pads = 2;
-    }
-    *nout = 0;
-    uint32_t val[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-        val[k] = 0;
-        if (k < r - pads) {
-            const uint32_t v = tab[byte_of(w, k)];
-            if (v & INVALID) return k;
-            val[k] = v;
-        }
-    }
-    if (nopad ? ((n & 3) == 1) : ((n & 3) != 0)) return r;
-    // Appendix A (strict): leftover bits of a padded final quad must be zero.
-    if ((mode & M_STRICT) && pads == 2 && ((tab[byte_of(w, r - 3)] * 16) & 255) != 0) return r - 3;
-    if ((mode & M_STRICT) && pads == 1 && ((tab[byte_of(w, r - 2)] * 64) & 255) != 0) return r - 2;
-    // groups of four (pads read as 0), then an unpadded trailing group of 2 or 3
-    uint32_t o[4] = {0u, 0u, 0u, 0u};
-    int cnt = 0;
-    const int full = r & ~3;
-#pragma unroll
-    for (int g = 0; g < 4; g++) {
-        const int k = 4 * g;
-        int nb = 0;
-        if (k + 4 <= full) nb = 3 - (k + 4 == r ? pads : 0);
-        else if (nopad && k == full && (r & 3) >= 2) nb = (r & 3) - 1;
-        if (nb == 0) continue;
-        const uint32_t t = (val[k] << 18) | (val[k + 1] << 12) | (val[k + 2] << 6) | val[k + 3];
-        const uint32_t b3[3] = {(t >> 16) & 255, (t >> 8) & 255, t & 255};
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            if (j < nb) {
-                const int at = cnt + j;  // at < 12
-                const uint32_t bits = b3[j] << (8 * (at & 3));
-                if (at < 4) o[0] |= bits; else if (at < 8) o[1] |= bits; else o[2] |= bits;
-            }
-        }
-        cnt += nb;
-    }
-    store_upto16(q, o, cnt);
-    *nout = cnt;
-    return -1;
-}
-
-// dec_tail_w through the full-unit routine: the characters from the padding
-// on (and past r) are read as 'A' (value 0), so one dec_unit gives the bytes
-// of every group, the first non-symbol among the rest is the first offending
-// index, and only the counts differ from an interior unit. Returns the first
-// offending index (relative to the unit, r for a length error at n), or
-// -1 - (bytes written) on success.
+// characters n-r .. n-1, held little-endian in w. Applies the padding rules
+// ('=' only as the last one or two characters of a length divisible by 4;
+// unpadded mode: '=' invalid, n mod 4 == 1 is a length error), the optional
+// strict leftover-bit check (Appendix A), and writes the decoded bytes to q.
+// The characters from the padding on (and past r) are read as 'A' (value
+// 0), so one dec_unit gives the bytes of every group, the first non-symbol
+// among the rest is the first offending index, and only the counts differ
+// from an interior unit. Returns the first offending index (relative to the
+// unit, r for a length error at n), or -1 - (bytes written) on success.
 __device__ __forceinline__ int dec_tail_fast(const uint32_t (&w)[4], int r, int64_t n, uint8_t *__restrict__ q,
                                              const uint8_t *tab, int mode)
 {
@@ -347,30 +252,17 @@ __device__ __forceinline__ int dec_tail_fast(const uint32_t (&w)[4], int r, int6
 // where a call costs more than the extra code (dec_tail below is the
 // out-of-line form for once-per-launch use).
 __device__ __forceinline__ int dec_tail_inl(const uint8_t *__restrict__ c, int r, int64_t n,
-                                            uint8_t *__restrict__ q, const uint8_t *tab, int mode,
-                                            int *nout)
+                                            uint8_t *__restrict__ q, const uint8_t *tab, int mode)
 {
     uint32_t w[4];
     load_upto16(c, r, w);
-    return dec_tail_w(w, r, n, q, tab, mode, nout);
+    return dec_tail_fast(w, r, n, q, tab, mode);
 }
 
 __device__ __noinline__ int dec_tail(const uint8_t *__restrict__ c, int r, int64_t n,
-                                     uint8_t *__restrict__ q, const uint8_t *tab, int mode,
-                                     int *nout)
+                                     uint8_t *__restrict__ q, const uint8_t *tab, int mode)
 {
-    return dec_tail_inl(c, r, n, q, tab, mode, nout);
-}
-
-// Out-of-line form for characters already in registers. Returns the first
-// offending index (>= 0), or -1 - (bytes written) on success.
-__device__ __noinline__ int dec_tail_r(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int r, int64_t n,
-                                       uint8_t *__restrict__ q, const uint8_t *tab, int mode)
-{
-    const uint32_t w[4] = {w0, w1, w2, w3};
-    int nout;
-    const int idx = dec_tail_w(w, r, n, q, tab, mode, &nout);
-    return idx >= 0 ? idx : -1 - nout;
+    return dec_tail_inl(c, r, n, q, tab, mode);
 }
 
 // -------------------------------------------- register and pair maps --

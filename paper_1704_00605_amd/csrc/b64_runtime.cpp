@@ -2,6 +2,7 @@
 // buddy allocator for device memory pools, and the continuous-batching
 // serving loop (see include/b64.h for the contracts).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <stdio.h>
 #include <string.h>
@@ -389,7 +390,7 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
         return op[r] == B64_DIR_ENCODE ? 4 * ((n + 2) / 3) : 3 * (n / 4) + 2;
     };
 
-    auto launch = [&](Slot &s, int dir, double t) -> int {
+    auto launch_batch = [&](Slot &s, int dir, double t) -> int {
         auto &q = ready[dir];
         const int64_t n = std::min<int64_t>(B, (int64_t)q.size());
         const Layout L{n};
@@ -451,6 +452,13 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
         (void)t;
         return B64_OK;
     };
+    // roctx ranges mark the three phases of the loop for a trace
+    auto launch = [&](Slot &s, int dir, double t) -> int {
+        roctxRangePushA(dir == B64_DIR_ENCODE ? "b64 serve: launch encode batch" : "b64 serve: launch decode batch");
+        const int lrc = launch_batch(s, dir, t);
+        roctxRangePop();
+        return lrc;
+    };
 
     while (completed < nreq) {
         const double t = now_s();
@@ -465,6 +473,7 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             hipError_t q = hipEventQuery(s.done);
             if (q == hipErrorNotReady) { inflight++; continue; }
             if (q != hipSuccess) { rc = hip_fail(q, "hipEventQuery"); break; }
+            roctxRangePushA("b64 serve: complete batch");
             const double td = now_s();
             const Layout L{(int64_t)s.reqs.size()};
             for (size_t i = 0; i < s.reqs.size(); i++) {
@@ -486,11 +495,14 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             completed += (int64_t)s.reqs.size();
             s.busy = false;
             s.reqs.clear();
+            roctxRangePop();
         }
         if (rc != B64_OK) break;
         st.max_inflight_batches = std::max<int64_t>(st.max_inflight_batches, inflight);
         // 2. admission in arrival order, by free pool memory
         bool blocked = false;
+        const bool admitting = next < nreq && t_arrival[next] * scale <= t;
+        if (admitting) roctxRangePushA("b64 serve: admit");
         while (next < nreq && t_arrival[next] * scale <= t) {
             int64_t off;
             const int64_t cap = out_cap(next);
@@ -505,6 +517,7 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             ready[op[next] == B64_DIR_ENCODE ? 0 : 1].push_back({next, t});
             next++;
         }
+        if (admitting) roctxRangePop();
         if (rc != B64_OK) break;
         // 3. launch batches on free slots
         const bool arrivals_done = next >= nreq;

@@ -103,11 +103,10 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
             dec_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, err_slot);
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        int nout;
         const int r = (int)(n - 16 * L);
-        const int idx = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode, &nout);
-        if (idx >= 0) atomicMin(err_slot, (unsigned long long)(16 * L + idx));
-        else *len_slot = 12 * L + nout;
+        const int res = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode);
+        if (res >= 0) atomicMin(err_slot, (unsigned long long)(16 * L + res));
+        else *len_slot = 12 * L + (-1 - res);
     }
 }
 
@@ -132,10 +131,9 @@ __global__ __launch_bounds__(1024) void k_dec_small(const uint8_t *__restrict__ 
     const MapCtx mc = map_ctx<0>(tab, nullptr, mode & M_URL, true);
     const int64_t L = (n - 1) / 16;
     if (threadIdx.x == 0) {
-        int nout;
-        const int idx = dec_tail(src + 16 * L, (int)(n - 16 * L), n, dst + 12 * L, tab, mode, &nout);
-        if (idx >= 0) atomicMin(&s_err, (unsigned long long)(16 * L + idx));
-        s_len = 12 * L + nout;
+        const int res = dec_tail(src + 16 * L, (int)(n - 16 * L), n, dst + 12 * L, tab, mode);
+        if (res >= 0) atomicMin(&s_err, (unsigned long long)(16 * L + res));
+        s_len = 12 * L + (res >= 0 ? 0 : -1 - res);
     }
     const int64_t tile = (int64_t)blockDim.x * 2;
     for (int64_t t0 = 0; t0 < L; t0 += tile) {

@@ -42,3 +42,26 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_serving_mismatch_count_closed_forms():
+    """The serving check's closed forms: encode lengths, clean decode
+    lengths, and the first injected byte inside a corrupted slice."""
+    import types
+
+    import numpy as np
+
+    banks = types.SimpleNamespace(text_len=1000, inject_pos=np.array([10, 50, 300], np.int64))
+    req = {"op": np.array([0, 0, 1, 1, 1, 1], np.uint8),
+           "in_len": np.array([5, 3, 40, 40, 100, 8], np.int64),
+           "in_begin": np.array([0, 7, 0, 1000 + 8, 1000 + 40, 1000 + 100], np.int64)}
+    # encode 5 -> 8, 3 -> 4; clean decode 40 -> 30; corrupted at 10 (offset 2),
+    # at 50 (offset 10), and a slice [100, 108) holding no injected byte
+    res = {"t_done": np.ones(6), "out_len": np.array([8, 4, 30, -1, -1, 6], np.int64),
+           "err_off": np.array([-1, -1, -1, 2, 10, -1], np.int64)}
+    assert bench.serving_mismatches(req, res, banks) == (0, 3)
+    res["err_off"][4] = 11
+    res["out_len"][0] = 9
+    assert bench.serving_mismatches(req, res, banks) == (2, 3)
+    res["t_done"][0] = -1.0  # not completed: not counted
+    assert bench.serving_mismatches(req, res, banks) == (1, 3)

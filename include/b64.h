@@ -201,7 +201,7 @@ int b64_batch_slots(int dir, const int64_t *h_len, const uint8_t *h_flags, int64
  *      unit from there at any alignment - best for many small and mid-size
  *      messages in packed batches. Packed batches only: gather batches with
  *      layout 2 run layout 1. Tiles past the first N + 4096 (more than the
- *      tile table holds) or starting more than 256 messages run a slower
+ *      tile table holds) or starting more than 64 messages run a slower
  *      per-lane path.
  * The autotuner picks all four per device and message-size histogram. */
 typedef struct b64_tune {

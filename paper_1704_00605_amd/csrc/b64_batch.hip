@@ -665,12 +665,11 @@ __global__ __launch_bounds__(1024) void k_dec_batch_t(
 // messages from the tile's first one on; each lane then finds its unit's
 // message by a binary search over the staged message starts and reads its
 // 12 (encode) or 16 (decode) bytes from LDS at any alignment. Tiles past the
-// table or starting more than S_META messages take the per-lane path of the
-// tile layout instead.
+// table or starting more than S_META messages take a per-lane path instead
+// (each lane searches its unit's message and reads its bytes from global
+// memory).
 constexpr int S_BLOCK = 256;
-constexpr int S_META = 256;
-
-__device__ __forceinline__ int64_t tile_cap(int64_t N) { return N + 4096; }
+constexpr int S_META = 64;  // messages one wave stages per tile
 
 // Bytes o .. o + 15 of an LDS byte buffer (any o with o + 20 inside it).
 __device__ __forceinline__ void lds_read16(const uint32_t *lds, uint32_t o, uint32_t (&w)[4])
@@ -694,11 +693,17 @@ __device__ __forceinline__ void keep_bytes(uint32_t (&w)[4], int r)
 }
 
 // Largest m in [lo, N) with unit_off[m] <= u (unit_off[lo] <= u < unit_off[N]),
-// by one lane on its own.
+// by one lane on its own: galloping from lo (one probe when u lies in
+// message lo, as in tiles inside a long message), then a binary search.
 __device__ __forceinline__ int64_t lane_search_msg(const int64_t *__restrict__ unit_off, int64_t N, int64_t u,
                                                    int64_t lo)
 {
-    int64_t hi = N;
+    int64_t hi = N, step = 1;
+    while (lo + step < N && unit_off[lo + step] <= u) {
+        lo += step;
+        step *= 2;
+    }
+    hi = min(N, lo + step);  // unit_off[lo] <= u < unit_off[hi]
     while (hi - lo > 1) {
         const int64_t mid = lo + ((hi - lo) >> 1);
         if (unit_off[mid] <= u) lo = mid;
@@ -742,13 +747,14 @@ __global__ __launch_bounds__(S_BLOCK) void k_batch_s(
             m0 = tile_m[t];
             const int64_t A = tile_A[t];
             const int64_t B = t + 1 < ntiles ? tile_A[t + 1] : in_off[N];
-            // one round of loads: the messages from m0 on (one per thread,
-            // plus one more by thread 0) and the tile's input chunks
+            // one round of loads: the messages from m0 on (one per lane of
+            // wave 0, plus one more by thread 0) and the tile's input chunks
             const int64_t idx = m0 + tid;
-            const int64_t mu = idx <= N ? unit_off[idx] : INT64_MAX;
-            const int64_t mb = idx <= N ? in_off[idx] : 0;
-            const int64_t mo = idx < N ? out_off[idx] : 0;
-            const int mf = (idx < N && flags) ? flags[idx] : 0;
+            const bool meta = tid < S_META;
+            const int64_t mu = (meta && idx <= N) ? unit_off[idx] : INT64_MAX;
+            const int64_t mb = (meta && idx <= N) ? in_off[idx] : 0;
+            const int64_t mo = (meta && idx < N) ? out_off[idx] : 0;
+            const int mf = (meta && idx < N && flags) ? flags[idx] : 0;
             int64_t mu_x = INT64_MAX, mb_x = 0;
             if (tid == 0 && m0 + S_META <= N) {
                 mu_x = unit_off[m0 + S_META];
@@ -769,10 +775,12 @@ __global__ __launch_bounds__(S_BLOCK) void k_batch_s(
                         (const void *)p, (__attribute__((address_space(3))) void *)(s_data + k * S_BLOCK + 64 * wv), 16, 0, 0);
                 }
             }
-            s_u[tid] = mu;
-            s_b[tid] = mb;
-            s_o[tid] = mo;
-            s_f[tid] = (uint8_t)mf;
+            if (meta) {
+                s_u[tid] = mu;
+                s_b[tid] = mb;
+                s_o[tid] = mo;
+                s_f[tid] = (uint8_t)mf;
+            }
             if (tid == 0) {
                 s_u[S_META] = mu_x;
                 s_b[S_META] = mb_x;

@@ -159,14 +159,36 @@ __device__ __forceinline__ int enc_tail_fast(const uint32_t (&w)[4], int r, uint
     return c;
 }
 
-// The same for the r bytes (0..11) at s in global memory (out of line: once
-// per message or per launch).
+// The same for the r bytes (1..11) at s in global memory, group by group
+// (out of line, once per message or per launch; its registers count against
+// every kernel that calls it, so it stays lean rather than fast).
 __device__ __noinline__ int enc_tail(const uint8_t *__restrict__ s, int r, uint8_t *__restrict__ q,
                                      const uint8_t *tab, int nopad)
 {
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-    if (r > 0) load_upto16(s, r, w);
-    return enc_tail_fast(w, r, q, tab, nopad);
+    uint32_t w[4];
+    load_upto16(s, r, w);
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int left = r - 3 * i;  // bytes from this group on
+        if (left <= 0) break;
+        const uint32_t v = (byte_of(w, 3 * i) << 16) | (byte_of(w, 3 * i + 1) << 8) | byte_of(w, 3 * i + 2);
+        const uint32_t ch[4] = {tab[v >> 18], tab[(v >> 12) & 63], left >= 2 ? tab[(v >> 6) & 63] : (uint32_t)'=',
+                                left >= 3 ? tab[v & 63] : (uint32_t)'='};
+        const int emit = nopad ? (left >= 3 ? 4 : left + 1) : 4;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (j < emit) {
+                const int at = c + j;  // at < 16
+                const uint32_t bits = ch[j] << (8 * (at & 3));
+                if (at < 4) o[0] |= bits; else if (at < 8) o[1] |= bits; else if (at < 12) o[2] |= bits; else o[3] |= bits;
+            }
+        }
+        c += emit;
+    }
+    store_upto16(q, o, c);
+    return c;
 }
 
 // ------------------------------------------------------ decode (a7,a9) --

@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "encode/decode GB/s & %HBM peak; batched vs per-msg launch; p50/p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_single_1GiB.json")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batched_ws.json")
 
 
 def progress(msg):
@@ -434,6 +435,8 @@ def report_batched(which, per_message=True):
             "hbm_frac": round(algo / tuned_ms / 1e6 / HBM_PEAK_GBPS, 4),
             "tune": best, "msgs_per_wg_step": entry.get("msgs_per_wg_step"),
             "same_verdicts_as_per_message": same,
+            "hbm_traffic": stored_batch_traffic(f"{which}.{label}", batch_kernel_name(direction, best),
+                                                best.get("block"), best.get("grid")),
         }
         if direction == codec.DIR_ENCODE:
             enc_dst, enc_off = dst, out_off
@@ -586,6 +589,8 @@ def report_ws():
         "hbm_frac": round(algo / ws_ms / 1e6 / HBM_PEAK_GBPS, 4),
         "plain_decode_same_text_ms": round(plain_ms, 4),
         "verified": bool(ok),
+        "hbm_traffic": {"count_pass": stored_batch_traffic("mime.count"),
+                        "decode_pass": stored_batch_traffic("mime.decode")},
     }
 
 
@@ -681,6 +686,54 @@ def stored_traffic(direction, n):
     if not entry or tf.get("size") != n or tf.get("kernel_hash") != kernel_hash():
         return None
     return entry.get("bytes_per_launch")
+
+
+def sources_hash(files):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        p = os.path.join(ROOT, "paper_1704_00605_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def batch_kernel_name(direction, tune):
+    """Name of the batched codec kernel a launch shape runs (layout 2:
+    k_batch_s<dir, units>; 1: k_*_batch_w<units>; 0: k_*_batch_t<units>)."""
+    upl = tune.get("units_per_lane") or 2
+    layout = tune.get("layout", 0)
+    if layout == 2:
+        return f"k_batch_s<{direction}, {upl}>"
+    d = "enc" if direction == 0 else "dec"
+    return f"k_{d}_batch_{'w' if layout == 1 else 't'}<{upl}>"
+
+
+def stored_batch_traffic(key, kernel=None, block=None, grid=None):
+    """HBM bytes per launch and their ratio to the payload for one batched or
+    whitespace configuration (key such as "uneven.encode" or "mime.decode"),
+    from the committed counter summary; None when the summary was taken on
+    other kernel sources or another kernel or launch shape."""
+    try:
+        tf = json.load(open(BATCH_TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = tf.get("entries", {}).get(key)
+    if not e:
+        return None
+    files = ["b64_modes.hpp", "b64_device.hpp", "b64_ws.hip" if key.startswith("mime") else "b64_batch.hip"]
+    want = tf.get("ws_kernel_hash" if key.startswith("mime") else "batch_kernel_hash")
+    if want != sources_hash(files):
+        return None
+    if kernel is not None and e.get("kernel") != kernel:
+        return None
+    if block is not None and grid is not None and kernel and "batch_s" not in kernel and \
+            (e.get("block") != block or e.get("grid_threads") != block * grid):
+        return None
+    return {"bytes_per_launch": e["bytes_per_launch"], "algorithmic_bytes": e["algorithmic_bytes"],
+            "ratio": e["ratio_to_algorithmic"], "kernel": e["kernel"],
+            "from": "profiles/hbm_traffic_batched_ws.json"}
 
 
 def kernel_hash():

@@ -65,3 +65,31 @@ def test_serving_mismatch_count_closed_forms():
     assert bench.serving_mismatches(req, res, banks) == (2, 3)
     res["t_done"][0] = -1.0  # not completed: not counted
     assert bench.serving_mismatches(req, res, banks) == (1, 3)
+
+
+def test_stored_batch_traffic_lookup(tmp_path, monkeypatch):
+    """Per-configuration traffic of the batched and whitespace kernels comes
+    from the committed summary only for the same kernel sources, kernel and
+    (for the tile and per-wave layouts) launch shape."""
+    tf = json.load(open(bench.BATCH_TRAFFIC_FILE))
+    for key, e in tf["entries"].items():
+        assert e["bytes_per_launch"] > 0 and 0.99 < e["ratio_to_algorithmic"] < 1.2, key
+    f = tmp_path / "b.json"
+    doc = {"batch_kernel_hash": bench.sources_hash(["b64_modes.hpp", "b64_device.hpp", "b64_batch.hip"]),
+           "ws_kernel_hash": "0" * 16,
+           "entries": {"uneven.encode": {"kernel": "k_batch_s<0, 4>", "grid_threads": 1, "block": 256,
+                                         "bytes_per_launch": 10, "algorithmic_bytes": 9, "ratio_to_algorithmic": 1.1},
+                       "heavy.decode": {"kernel": "k_dec_batch_t<4>", "grid_threads": 4096 * 1024, "block": 1024,
+                                        "bytes_per_launch": 5, "algorithmic_bytes": 5, "ratio_to_algorithmic": 1.0},
+                       "mime.decode": {"kernel": "k_dec_ws", "bytes_per_launch": 3, "algorithmic_bytes": 3,
+                                       "ratio_to_algorithmic": 1.0}}}
+    f.write_text(json.dumps(doc))
+    monkeypatch.setattr(bench, "BATCH_TRAFFIC_FILE", str(f))
+    k2 = bench.batch_kernel_name(0, {"layout": 2, "units_per_lane": 4})
+    assert k2 == "k_batch_s<0, 4>" and bench.stored_batch_traffic("uneven.encode", k2, 256, 99)["bytes_per_launch"] == 10
+    assert bench.stored_batch_traffic("uneven.encode", "k_batch_s<0, 2>", 256, 99) is None  # other kernel
+    k0 = bench.batch_kernel_name(1, {"layout": 0, "units_per_lane": 4})
+    assert bench.stored_batch_traffic("heavy.decode", k0, 1024, 4096)["ratio"] == 1.0
+    assert bench.stored_batch_traffic("heavy.decode", k0, 512, 4096) is None  # other shape
+    assert bench.stored_batch_traffic("mime.decode") is None  # other whitespace sources
+    assert bench.stored_batch_traffic("uneven.decode") is None  # not measured

@@ -282,15 +282,29 @@ def main():
 # ---------------------------------------------------------------- reports --
 
 def _events_ms(fn, reps, stream):
+    """Median device time of one call of fn over reps back-to-back calls on
+    stream (HIP events between consecutive calls). A spin kernel queued first
+    keeps the device behind the host, so that the calls run back to back and
+    an interval is device time, not the host's time to issue a call; the
+    spin is lengthened until it is still running when the host has issued
+    every call."""
     import torch
     fn()
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-    ev[0].record(stream)
-    for i in range(reps):
-        fn()
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
+    spin = 200_000 * reps
+    for _ in range(4):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(spin)
+        ev[0].record(stream)
+        for i in range(reps):
+            fn()
+            ev[i + 1].record(stream)
+        behind = not ev[0].query()
+        torch.cuda.synchronize()
+        if behind:
+            break
+        spin *= 4
     return float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]))
 
 

@@ -44,7 +44,8 @@
  *       b64_graph_create_batch: a private capture stream and the graph;
  *       b64_server_run: per-stream staging buffers, freed before it returns.
  *     The asynchronous and batched calls take caller-owned workspaces;
- *     b64_decode_batch_noalloc uses a static device array instead.
+ *     b64_decode_batch_noalloc uses a static device array instead, and the
+ *     single-buffer decodes a static 32 KiB array of verdict cells.
  */
 #ifndef B64HIP_H
 #define B64HIP_H
@@ -115,7 +116,17 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
 /* Non-blocking decode. d_len and d_err are DEVICE int64 slots that receive
  * (decoded length, -1) or (-1, first offending index) when the stream
  * reaches the end of the work. Returns B64_OK once enqueued, or an argument /
- * runtime error code. */
+ * runtime error code.
+ * Launches: one for inputs up to 32 MiB of text on a stream that holds a
+ * verdict cell (the last workgroup to finish forms the verdict); without a
+ * cell, one up to 262,160 characters (a single workgroup); three otherwise
+ * (slot set-up, decode, verdict). Each device has 1,024 verdict cells, given
+ * out to the first 1,024 distinct stream handles that decode on it and kept
+ * for the life of the process. Streams being captured into a graph and the
+ * per-thread default stream get none. A cell is reused only by later work on
+ * the same stream handle: a stream destroyed while its decode still runs
+ * must not have its handle reused for a decode before that work ends.
+ * b64_decode and b64_decode_ex take the same path on their stream. */
 int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, int64_t *d_len,
                      int64_t *d_err, void *stream);
 

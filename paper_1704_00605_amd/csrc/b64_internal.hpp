@@ -41,9 +41,6 @@ int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, h
 int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, unsigned long long *err_slot,
                         int64_t *len_slot, hipStream_t s);
 
-int b64i_enqueue_decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
-                              int64_t *d_err, hipStream_t s);
-
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \

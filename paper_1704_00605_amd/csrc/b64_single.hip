@@ -5,7 +5,13 @@
 //   k_dec_single  Algorithm 2 over one buffer: grid-stride over interior
 //                 16-character units, then the final unit with the padding
 //                 and length rules.
-//   k_dec_final   verdict (length, -1) or (-1, first offending index).
+//   k_dec_small   one-workgroup decode of a short input, verdict included.
+//   k_dec_final   verdict (length, -1) or (-1, first offending index) of a
+//                 decode whose stream has no verdict cell.
+//
+// A decode's verdict is formed inside k_dec_single itself when its stream
+// holds a verdict cell: the workgroup that finishes last reads the cell
+// (see VerdictCell), so an asynchronous decode is one launch at any size.
 //
 // Decode errors: a lane whose unit holds a non-symbol computes the exact
 // index; a wave ballot elects the first erring lane, which performs one
@@ -15,6 +21,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "b64.h"
@@ -77,43 +84,103 @@ __global__ __launch_bounds__(1024) void k_enc_single(const uint8_t *__restrict__
         enc_tail(src + 12 * units, r, dst + 16 * units, tab, mode & M_NOPAD);
 }
 
+// Verdict cell of a one-launch decode: the workgroups of one launch meet in
+// it to form the verdict without a second kernel. At rest (before and after
+// every launch) it is all zero, which is also the state a static device
+// array starts in, so it needs no initialisation. The first offending index
+// e is kept as ERR_NONE - e under atomicMax (0 = no error yet), so that the
+// resting value means "none".
+struct VerdictCell {
+    unsigned long long err;   // ERR_NONE - smallest offending index, or 0
+    unsigned long long len;   // decoded length, written by the final unit when valid
+    unsigned int done;        // workgroups finished
+    unsigned int pad[3];
+};
+constexpr int VERDICT_CELLS = 1024;
+static __device__ __align__(256) VerdictCell g_cells[VERDICT_CELLS];
+
 // Decode src[0, n), n >= 1. Interior units [0, L) with L = (n - 1) / 16 hold
 // 16 characters that are all before the final one; unit L (1..16 characters)
-// carries the padding and length rules. err_slot must hold ERR_NONE at
-// launch; it ends holding the smallest offending index (or ERR_NONE). The
-// lane of the final unit writes the decoded length to *len_slot when that
-// unit is valid. k_dec_final turns the pair into the verdict.
-template <bool ALIGNED, int UPL, int MAP>
+// carries the padding and length rules.
+//   CELL == false: err_slot must hold ERR_NONE at launch; it ends holding the
+//     smallest offending index (or ERR_NONE). The lane of the final unit
+//     writes the decoded length to *len_slot when that unit is valid, and
+//     k_dec_final turns the pair into the verdict.
+//   CELL == true: each workgroup keeps its smallest offending index in LDS,
+//     folds it into *cell and counts itself done there; the workgroup that
+//     finishes last writes the verdict (length, -1) or (-1, index) to
+//     d_len / d_err and returns the cell to rest. The cell must be at rest at
+//     launch and used by no other launch until this one ends.
+template <bool ALIGNED, int UPL, int MAP, bool CELL>
 __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, int mode,
-                                                     unsigned long long *err_slot, int64_t *len_slot)
+                                                     unsigned long long *err_slot, int64_t *len_slot,
+                                                     VerdictCell *cell, int64_t *d_len, int64_t *d_err)
 {
     __shared__ uint32_t s_tab[64];
+    __shared__ unsigned long long s_err;
     lds_fill(s_tab, c_tab.dec[mode & M_URL], 256);
+    if (CELL && threadIdx.x == 0) s_err = ERR_NONE;
     __syncthreads();
     const uint8_t *tab = (const uint8_t *)s_tab;
     const MapCtx mc = map_ctx<MAP>(tab, nullptr, mode & M_URL, true);
+    unsigned long long *const es = CELL ? &s_err : err_slot;
 
     const int64_t L = (n - 1) / 16;
     const int64_t tile = (int64_t)blockDim.x * UPL;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < L; t0 += (int64_t)gridDim.x * tile) {
         if (t0 + tile <= L)
-            dec_step<ALIGNED, UPL, false, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, err_slot);
+            dec_step<ALIGNED, UPL, false, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es);
         else
-            dec_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, err_slot);
+            dec_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es);
     }
+    int64_t len = -1;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         const int r = (int)(n - 16 * L);
         const int res = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode);
-        if (res >= 0) atomicMin(err_slot, (unsigned long long)(16 * L + res));
+        if (res >= 0) atomicMin(es, (unsigned long long)(16 * L + res));
+        else if (CELL) len = 12 * L + (-1 - res);
         else *len_slot = 12 * L + (-1 - res);
+    }
+    if constexpr (CELL) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // The cell is only touched through device-scope atomics, which act
+            // on one coherent copy. This workgroup's reports are waited for
+            // (their returned values consumed) before it counts itself, so the
+            // workgroup that counts last finds every report in the cell. No
+            // release fence: that would write back this XCD's L2 on every count.
+            const unsigned long long e = s_err;
+            unsigned long long seen = 0;
+            if (e != ERR_NONE)
+                seen |= __hip_atomic_fetch_max(&cell->err, ERR_NONE - e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (len >= 0)
+                seen |= __hip_atomic_exchange(&cell->len, (unsigned long long)len, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            asm volatile("" ::"v"(seen) : "memory");
+            const unsigned prev = __hip_atomic_fetch_add(&cell->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == gridDim.x - 1) {
+                const unsigned long long v = __hip_atomic_exchange(&cell->err, 0ull, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long l = __hip_atomic_exchange(&cell->len, 0ull, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_exchange(&cell->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v == 0) { *d_len = (int64_t)l; *d_err = -1; }
+                else { *d_len = -1; *d_err = (int64_t)(ERR_NONE - v); }
+            }
+        }
     }
 }
 
-// Decode of a short input (at most SMALL_UNITS interior units) by one
-// workgroup, verdict included, so that the whole call is one launch: the
-// first offending index is kept in an LDS slot (unsigned atomicMin) and
-// thread 0 writes (length, -1) or (-1, index) at the end.
+// Decode of a short input by one workgroup, verdict included, so that the
+// whole call is one launch: the first offending index is kept in an LDS slot
+// (unsigned atomicMin) and thread 0 writes (length, -1) or (-1, index) at
+// the end. It takes inputs of at most SMALL_UNITS_CELL interior units (one
+// pass of its 1,024 lanes x 2 units), and up to SMALL_UNITS on a stream
+// without a verdict cell, where the alternative is three launches. Between
+// the two, the one-launch grid of k_dec_single is faster (6.1 against
+// 6.4-11.8 us for 64-256 KiB of text on MI355X).
+constexpr int64_t SMALL_UNITS_CELL = 2048;
 constexpr int64_t SMALL_UNITS = 16384;
 
 template <bool ALIGNED>
@@ -150,18 +217,17 @@ __global__ __launch_bounds__(1024) void k_dec_small(const uint8_t *__restrict__ 
     }
 }
 
-// Verdict of a single-buffer decode, run after k_dec_single on the same
-// stream: (length, -1) or (-1, first offending index). With reset, the error
-// slot is restored to ERR_NONE for the next call.
-__global__ void k_dec_final(unsigned long long *err_slot, const int64_t *len_slot, int64_t *out_len,
-                            int64_t *out_err, int reset)
+// Verdict of a single-buffer decode, run after k_dec_single (without a
+// verdict cell) on the same stream: (length, -1) or (-1, first offending
+// index).
+__global__ void k_dec_final(const unsigned long long *err_slot, const int64_t *len_slot, int64_t *out_len,
+                            int64_t *out_err)
 {
     if (threadIdx.x == 0) {
         const unsigned long long e = *err_slot;
         const int64_t len = *len_slot;
         if (e == ERR_NONE) { *out_len = len; *out_err = -1; }
         else { *out_len = -1; *out_err = (int64_t)e; }
-        if (reset) *err_slot = ERR_NONE;
     }
 }
 
@@ -192,12 +258,12 @@ struct Shape {
 };
 Shape g_single[2] = {512, 256};
 
-// Per-thread, per-device result slots of the synchronous decode:
-// [0] error slot (u64, kept at ERR_NONE between calls), [1] length written by
-// the final unit, [2] verdict length, [3] verdict error offset.
+// Per-thread, per-device verdict slots of the synchronous decode: d[0]
+// length, d[1] first offending index (written by every call), and the pinned
+// host words they are read back into.
 struct SyncSlot {
     int dev = -1;
-    unsigned long long *d = nullptr;
+    int64_t *d = nullptr;
     int64_t *h = nullptr;
 };
 thread_local std::vector<SyncSlot> t_slots;
@@ -211,10 +277,8 @@ int sync_slot(SyncSlot **out)
     // kept only once every step succeeded (a failed step frees what it got)
     SyncSlot s;
     s.dev = dev;
-    const unsigned long long init[4] = {ERR_NONE, 0ull, 0ull, 0ull};
     hipError_t e = hipMalloc((void **)&s.d, 64);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s.h, 16, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemcpy(s.d, init, sizeof init, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (s.h) (void)hipHostFree(s.h);
         if (s.d) (void)hipFree(s.d);
@@ -261,16 +325,26 @@ void launch_enc_single(int upl, int map, int grid, int block, const uint8_t *src
     }
 }
 
-template <bool A>
+#define B64_UPL_SWITCH_DEC(A, M, C, ...)                                                         \
+    switch (upl) {                                                                               \
+    case 1: hipLaunchKernelGGL((k_dec_single<A, 1, M, C>), grid, block, 0, s, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL((k_dec_single<A, 2, M, C>), grid, block, 0, s, __VA_ARGS__); break; \
+    case 8: hipLaunchKernelGGL((k_dec_single<A, 8, M, C>), grid, block, 0, s, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((k_dec_single<A, 4, M, C>), grid, block, 0, s, __VA_ARGS__); break; \
+    }
+
+template <bool A, bool C>
 void launch_dec_single(int upl, int map, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
-                       int mode, unsigned long long *slot, int64_t *len_slot, hipStream_t s)
+                       int mode, unsigned long long *slot, int64_t *len_slot, VerdictCell *cell,
+                       int64_t *d_len, int64_t *d_err, hipStream_t s)
 {
     if (map == 1) {
-        B64_UPL_SWITCH(k_dec_single, A, 1, src, n, dst, mode, slot, len_slot);
+        B64_UPL_SWITCH_DEC(A, 1, C, src, n, dst, mode, slot, len_slot, cell, d_len, d_err);
     } else {
-        B64_UPL_SWITCH(k_dec_single, A, 0, src, n, dst, mode, slot, len_slot);
+        B64_UPL_SWITCH_DEC(A, 0, C, src, n, dst, mode, slot, len_slot, cell, d_len, d_err);
     }
 }
+#undef B64_UPL_SWITCH_DEC
 #undef B64_UPL_SWITCH
 
 bool aligned4(const void *a, const void *b)
@@ -301,16 +375,97 @@ int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, u
     int rc = single_grid(1, (n - 1) / 16, &block, &upl, &grid);
     if (rc) return rc;
     const int map = g_single[1].map.load();
-    if (aligned4(src, dst)) launch_dec_single<true>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, s);
-    else launch_dec_single<false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, s);
+    if (aligned4(src, dst))
+        launch_dec_single<true, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr,
+                                       nullptr, nullptr, s);
+    else
+        launch_dec_single<false, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr,
+                                        nullptr, nullptr, s);
     LAUNCH_TRY();
     return B64_OK;
 }
 
-// One-launch decode of a short input (n >= 1, at most SMALL_UNITS interior
+namespace {
+
+// Verdict cells are handed out per (device, stream): launches on one stream
+// run one after another, so a cell is back at rest before the next launch
+// on its stream starts, while launches on different streams never share
+// one. Streams beyond VERDICT_CELLS per device, the per-thread default
+// stream (one handle for many streams) and streams being captured (a graph
+// may be replayed anywhere) get no cell; their decodes take three launches.
+struct CellTable {
+    std::mutex mu;
+    int dev = -1;
+    VerdictCell *base = nullptr;
+    std::vector<hipStream_t> owner;
+};
+std::mutex g_cells_mu;
+std::vector<CellTable *> g_cell_tables;
+
+VerdictCell *stream_cell(hipStream_t s)
+{
+    if (s == hipStreamPerThread) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (cs != hipStreamCaptureStatusNone) return nullptr;
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    CellTable *t = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_cells_mu);
+        for (CellTable *c : g_cell_tables)
+            if (c->dev == dev) t = c;
+        if (!t) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_cells)) != hipSuccess || !p) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            t = new CellTable;
+            t->dev = dev;
+            t->base = (VerdictCell *)p;
+            g_cell_tables.push_back(t);
+        }
+    }
+    std::lock_guard<std::mutex> g(t->mu);
+    for (size_t i = 0; i < t->owner.size(); i++)
+        if (t->owner[i] == s) return t->base + i;
+    if (t->owner.size() >= (size_t)VERDICT_CELLS) return nullptr;
+    t->owner.push_back(s);
+    return t->base + (t->owner.size() - 1);
+}
+
+// The counts of a verdict cell are atomics on one address, which the device
+// serialises (13-16 ns apart on MI355X): a grid of G workgroups adds about
+// G * 15 ns. The one-launch decode therefore keeps to the set launch shape
+// only while that needs at most one workgroup per CU, then takes workgroups
+// of 1,024 lanes x 4 units (64 KiB of text), up to this many. Larger inputs
+// are decoded faster by the one-shot grid of small workgroups and the two
+// extra launches.
+constexpr int CELL_MAX_BLOCKS = 512;
+
+int decode_three_launches(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
+                          int64_t *d_err, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, 0);
+    LAUNCH_TRY();
+    int rc = b64i_enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, d_len, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, (const unsigned long long *)d_err, d_len, d_len, d_err);
+    LAUNCH_TRY();
+    return B64_OK;
+}
+
+// One-workgroup decode of src[0, n) (n >= 1, at most SMALL_UNITS interior
 // units) with its verdict written to d_len / d_err.
-int b64i_enqueue_decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
-                              int64_t *d_err, hipStream_t s)
+int decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len, int64_t *d_err,
+                 hipStream_t s)
 {
     if (aligned4(src, dst))
         hipLaunchKernelGGL(k_dec_small<true>, 1, 1024, 0, s, src, n, dst, mode, d_len, d_err);
@@ -319,6 +474,45 @@ int b64i_enqueue_decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int m
     LAUNCH_TRY();
     return B64_OK;
 }
+
+// Decode of src[0, n) (n >= 1) with its verdict in d_len / d_err:
+//   - at most SMALL_UNITS_CELL interior units: one workgroup (k_dec_small);
+//   - on a stream with a verdict cell, up to 32 MiB of text: one launch of
+//     k_dec_single, which forms the verdict itself;
+//   - otherwise, at most SMALL_UNITS interior units: one workgroup;
+//   - otherwise the slot initialisation, k_dec_single and k_dec_final.
+int decode_with_verdict(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
+                        int64_t *d_err, hipStream_t s)
+{
+    const int64_t units = (n - 1) / 16;
+    if (units <= SMALL_UNITS_CELL) return decode_small(src, n, dst, mode, d_len, d_err, s);
+    if (VerdictCell *cell = stream_cell(s)) {
+        int block, upl, grid, cus;
+        int rc = single_grid(1, units, &block, &upl, &grid);
+        if (!rc) rc = b64i_device_cus(&cus);
+        if (rc) return rc;
+        if (grid > cus) {  // fewer, larger workgroups
+            block = 1024;
+            upl = 4;
+            grid = (int)std::min<int64_t>((units + 4095) / 4096, INT32_MAX);
+        }
+        if (grid <= CELL_MAX_BLOCKS) {
+            const int map = g_single[1].map.load();
+            if (aligned4(src, dst))
+                launch_dec_single<true, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell,
+                                              d_len, d_err, s);
+            else
+                launch_dec_single<false, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell,
+                                               d_len, d_err, s);
+            LAUNCH_TRY();
+            return B64_OK;
+        }
+    }
+    if (units <= SMALL_UNITS) return decode_small(src, n, dst, mode, d_len, d_err, s);
+    return decode_three_launches(src, n, dst, mode, d_len, d_err, s);
+}
+
+}  // namespace
 
 // ================================================================ C-ABI ==
 extern "C" {
@@ -359,17 +553,9 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
     rc = sync_slot(&sl);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if ((n - 1) / 16 <= SMALL_UNITS) {
-        rc = b64i_enqueue_decode_small(src, n, dst, mode, (int64_t *)(sl->d + 2), (int64_t *)(sl->d + 3), s);
-        if (rc) return rc;
-    } else {
-        rc = b64i_enqueue_decode(src, n, dst, mode, sl->d, (int64_t *)(sl->d + 1), s);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, sl->d, (const int64_t *)(sl->d + 1), (int64_t *)(sl->d + 2),
-                           (int64_t *)(sl->d + 3), 1);
-        LAUNCH_TRY();
-    }
-    HIP_TRY(hipMemcpyAsync(sl->h, sl->d + 2, 16, hipMemcpyDeviceToHost, s));
+    rc = decode_with_verdict(src, n, dst, mode, sl->d, sl->d + 1, s);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(sl->h, sl->d, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const int64_t len = sl->h[0], err = sl->h[1];
     if (len < 0) {
@@ -395,18 +581,12 @@ int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, 
     if (n > 0 && (!src || (!dst && b64_decoded_max_mode(n, alphabet & ~0xff) > 0)))
         return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
     hipStream_t s = (hipStream_t)stream;
-    if (n > 0 && (n - 1) / 16 <= SMALL_UNITS) {
-        rc = b64i_enqueue_decode_small(src, n, dst, mode, d_len, d_err, s);
-        return rc;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, 1);
+        LAUNCH_TRY();
+        return B64_OK;
     }
-    hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, n == 0 ? 1 : 0);
-    LAUNCH_TRY();
-    if (n == 0) return B64_OK;
-    rc = b64i_enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, d_len, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, (unsigned long long *)d_err, d_len, d_len, d_err, 0);
-    LAUNCH_TRY();
-    return B64_OK;
+    return decode_with_verdict(src, n, dst, mode, d_len, d_err, s);
 }
 
 int b64_set_single_tune(int dir, const b64_tune *t)

@@ -558,6 +558,70 @@ __device__ __forceinline__ void store_words(uint8_t *q, const uint32_t (&o)[K])
     store_edge_lo((uint8_t *)(d + K), o[K - 1] >> (8 * sh), s);
 }
 
+// K dwords' worth of bytes (K = 1 or 2) at any address p, read as the aligned
+// dwords that hold them.
+template <int K>
+__device__ __forceinline__ void load_words(const uint8_t *p, uint32_t (&w)[K])
+{
+    const uint32_t s = (uint32_t)((uintptr_t)p & 3);
+    const uint32_t *a = (const uint32_t *)(p - s);
+    if (s == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) w[k] = a[k];
+    } else {
+        uint32_t v[K + 1];
+#pragma unroll
+        for (int k = 0; k <= K; k++) v[k] = a[k];
+#pragma unroll
+        for (int k = 0; k < K; k++) w[k] = alignb(v[k + 1], v[k], s);
+    }
+}
+
+// Lane i gets lane i - 1's x (lane 0 gets 0): one DPP move shifting the
+// whole wave by a lane, with every lane active.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+
+// Stores of a wave's consecutive output runs (lane i's 4K bytes directly
+// after lane i - 1's) at a destination that is not 4-byte aligned; the
+// misalignment s = q & 3 is the same in every lane. Lane i writes the aligned
+// window [q - s, q - s + 4K) as whole dwords in one vector store: its first
+// s bytes end the run before its own, whose last word pw the caller supplies
+// (the left neighbour's, by a wave shift; lane 0 recomputes it). So no
+// dword is written by two waves, which on MI355X costs far more than the
+// extra work: each would hold a partial dword in its XCD's L2. Only where
+// the run before is not the caller's (the first unit of a buffer) does the
+// lane write its head with byte/short stores (whole_head == false), and only
+// at the end of the buffer's units its last s bytes (tail == true), so no byte
+// outside the runs is written.
+template <int K>
+__device__ __forceinline__ void store_run_wave(uint8_t *q, const uint32_t (&o)[K], uint32_t pw, bool whole_head,
+                                               bool tail)
+{
+    const uint32_t s = (uint32_t)((uintptr_t)q & 3);
+    const uint32_t sh = 4 - s;
+    uint32_t *d = (uint32_t *)(q - s);
+    uint32_t w[K];
+    w[0] = alignb(o[0], pw, sh);
+#pragma unroll
+    for (int k = 1; k < K; k++) w[k] = alignb(o[k], o[k - 1], sh);
+    if (whole_head) {
+        __builtin_nontemporal_store(w[0], d);
+    } else if (s == 1) {
+        q[0] = (uint8_t)o[0];
+        *(uint16_t *)(q + 1) = (uint16_t)(o[0] >> 8);
+    } else if (s == 2) {
+        *(uint16_t *)q = (uint16_t)o[0];
+    } else {
+        q[0] = (uint8_t)o[0];
+    }
+#pragma unroll
+    for (int k = 1; k < K; k++) __builtin_nontemporal_store(w[k], d + k);
+    if (tail) store_edge_lo((uint8_t *)(d + K), o[K - 1] >> (8 * sh), s);
+}
+
 // ------------------------------------------------------ buffer steps --
 // Copies `bytes` (multiple of 4) of the constant tables into LDS.
 __device__ __forceinline__ void lds_fill(uint32_t *dst, const uint8_t *src, int bytes)
@@ -569,14 +633,27 @@ __device__ __forceinline__ void lds_fill(uint32_t *dst, const uint8_t *src, int 
 // One grid-stride step of the encode over one buffer: this lane's units are
 // first + k * stride for k < UPL. Without GUARD every unit is known to be in
 // range, so all UPL loads are issued before any is consumed.
-template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0>
+// SPLIT (the destination is not 4-byte aligned; the caller checks): every
+// lane of the wave calls the step, lane l's first is the wave's first plus l,
+// and the output goes through store_run_wave, with the words between lanes
+// passed by a wave shift. The last s bytes of a unit are then written with
+// the next unit, which must also be written by such a step: cover_end is the
+// end of the run of units that these steps write, whose last unit's lane
+// writes them itself. The SPLIT code is a separate instantiation because
+// compiled into the same kernel as the others it costs them registers and
+// speed even where it does not run.
+template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0, bool SPLIT = false>
 __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
-                                         int64_t first, int stride, int64_t units, const MapCtx &mc)
+                                         int64_t first, int stride, int64_t units, const MapCtx &mc,
+                                         int64_t cover_end = 0)
 {
+    static_assert(!(ALIGNED && SPLIT), "a split store needs a misaligned destination");
     uint32_t w[UPL][3];
+    uint32_t lw[UPL];  // SPLIT, lane 0: the last input dword of the unit before its own
 #pragma unroll
     for (int k = 0; k < UPL; k++) {
         const int64_t u = first + (int64_t)k * stride;
+        lw[k] = 0;
         if (!GUARD || u < units) {
             if (ALIGNED) {  // streamed: read once, so non-temporal
                 const uint32_t *p = (const uint32_t *)(src + 12 * u);
@@ -585,40 +662,64 @@ __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_
                 w[k][2] = __builtin_nontemporal_load(p + 2);
             } else {
                 load12(src + 12 * u, w[k][0], w[k][1], w[k][2]);
+                if (SPLIT && __lane_id() == 0 && u > 0) {
+                    uint32_t x[1];
+                    load_words<1>(src + 12 * u - 4, x);
+                    lw[k] = x[0];
+                }
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < UPL; k++) {
         const int64_t u = first + (int64_t)k * stride;
-        if (!GUARD || u < units) {
-            uint32_t o[4];
-            enc_unit_m<MAP>(w[k][0], w[k][1], w[k][2], mc, o[0], o[1], o[2], o[3]);
-            if (ALIGNED) {
-                uint32_t *d = (uint32_t *)(dst + 16 * u);
-                __builtin_nontemporal_store(o[0], d + 0);
-                __builtin_nontemporal_store(o[1], d + 1);
-                __builtin_nontemporal_store(o[2], d + 2);
-                __builtin_nontemporal_store(o[3], d + 3);
-            } else {
-                store_words<4>(dst + 16 * u, o);
+        if constexpr (!SPLIT) {
+            if (!GUARD || u < units) {
+                uint32_t o[4];
+                enc_unit_m<MAP>(w[k][0], w[k][1], w[k][2], mc, o[0], o[1], o[2], o[3]);
+                if (ALIGNED) {
+                    uint32_t *d = (uint32_t *)(dst + 16 * u);
+                    __builtin_nontemporal_store(o[0], d + 0);
+                    __builtin_nontemporal_store(o[1], d + 1);
+                    __builtin_nontemporal_store(o[2], d + 2);
+                    __builtin_nontemporal_store(o[3], d + 3);
+                } else {
+                    store_words<4>(dst + 16 * u, o);
+                }
+            }
+        } else {
+            const bool live = !GUARD || u < units;
+            uint32_t o[4] = {0, 0, 0, 0};
+            if (live) enc_unit_m<MAP>(w[k][0], w[k][1], w[k][2], mc, o[0], o[1], o[2], o[3]);
+            uint32_t pw = wave_shr1(o[3]);
+            if (live) {
+                const bool lane0 = __lane_id() == 0;
+                if (lane0 && u > 0) {  // the last quad of the unit before: its last 3 bytes
+                    uint32_t a, b, c;
+                    enc_unit_m<MAP>(lw[k], lw[k], lw[k], mc, a, b, c, pw);
+                }
+                store_run_wave<4>(dst + 16 * u, o, pw, !lane0 || u > 0, u + 1 == cover_end);
             }
         }
     }
 }
 
-// One grid-stride step of the decode over one buffer (see enc_step). Lanes of a
-// wave hold consecutive units, so the lowest erring lane of a ballot has the
-// wave's smallest offset; it alone performs the atomicMin.
-template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0>
+// One grid-stride step of the decode over one buffer (see enc_step for the
+// guard, SPLIT and cover_end). Lanes of a wave hold consecutive units, so the
+// lowest erring lane of a ballot has the wave's smallest offset; it alone
+// performs the atomicMin.
+template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0, bool SPLIT = false>
 __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
                                          int64_t first, int stride, int64_t L, const MapCtx &mc,
-                                         unsigned long long *err_slot)
+                                         unsigned long long *err_slot, int64_t cover_end = 0)
 {
+    static_assert(!(ALIGNED && SPLIT), "a split store needs a misaligned destination");
     uint32_t w[UPL][4];
+    uint32_t lw[UPL][2];  // SPLIT, lane 0: the last 8 characters of the unit before its own
 #pragma unroll
     for (int k = 0; k < UPL; k++) {
         const int64_t u = first + (int64_t)k * stride;
+        lw[k][0] = lw[k][1] = 0;
         if (!GUARD || u < L) {
             if (ALIGNED) {  // streamed: read once, so non-temporal
                 const uint32_t *p = (const uint32_t *)(src + 16 * u);
@@ -628,6 +729,7 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
                 w[k][3] = __builtin_nontemporal_load(p + 3);
             } else {
                 load16(src + 16 * u, w[k][0], w[k][1], w[k][2], w[k][3]);
+                if (SPLIT && __lane_id() == 0 && u > 0) load_words<2>(src + 16 * u - 8, lw[k]);
             }
         }
     }
@@ -637,17 +739,35 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
     for (int k = 0; k < UPL; k++) {
         const int64_t u = first + (int64_t)k * stride;
         bad[k] = 0;
-        if (!GUARD || u < L) {
-            uint32_t o[3];
-            bad[k] = dec_unit_m<MAP>(w[k][0], w[k][1], w[k][2], w[k][3], mc, o[0], o[1], o[2]);
-            bad_any |= bad[k];
-            if (ALIGNED) {
-                uint32_t *d = (uint32_t *)(dst + 12 * u);
-                __builtin_nontemporal_store(o[0], d + 0);
-                __builtin_nontemporal_store(o[1], d + 1);
-                __builtin_nontemporal_store(o[2], d + 2);
-            } else {
-                store_words<3>(dst + 12 * u, o);
+        if constexpr (!SPLIT) {
+            if (!GUARD || u < L) {
+                uint32_t o[3];
+                bad[k] = dec_unit_m<MAP>(w[k][0], w[k][1], w[k][2], w[k][3], mc, o[0], o[1], o[2]);
+                bad_any |= bad[k];
+                if (ALIGNED) {
+                    uint32_t *d = (uint32_t *)(dst + 12 * u);
+                    __builtin_nontemporal_store(o[0], d + 0);
+                    __builtin_nontemporal_store(o[1], d + 1);
+                    __builtin_nontemporal_store(o[2], d + 2);
+                } else {
+                    store_words<3>(dst + 12 * u, o);
+                }
+            }
+        } else {
+            const bool live = !GUARD || u < L;
+            uint32_t o[3] = {0, 0, 0};
+            if (live) {
+                bad[k] = dec_unit_m<MAP>(w[k][0], w[k][1], w[k][2], w[k][3], mc, o[0], o[1], o[2]);
+                bad_any |= bad[k];
+            }
+            uint32_t pw = wave_shr1(o[2]);
+            if (live) {
+                const bool lane0 = __lane_id() == 0;
+                if (lane0 && u > 0) {  // the last three bytes of the unit before: its last two quads
+                    uint32_t a, b;
+                    (void)dec_unit_m<MAP>(lw[k][0], lw[k][1], lw[k][0], lw[k][1], mc, a, b, pw);
+                }
+                store_run_wave<3>(dst + 12 * u, o, pw, !lane0 || u > 0, u + 1 == cover_end);
             }
         }
     }

@@ -58,8 +58,9 @@ __device__ __forceinline__ MapCtx map_ctx(const uint8_t *tab, const uint16_t *ta
 
 // Encode src[0, n): full units [0, n / 12) in a grid-stride loop over tiles
 // of blockDim * UPL units, then the final partial unit (Algorithm 1's tail)
-// by one lane.
-template <bool ALIGNED, int UPL, int MAP>
+// by one lane. AL: 0 source and destination 4-byte aligned, 1 only the
+// destination, 2 a misaligned destination (written whole dwords per wave).
+template <int AL, int UPL, int MAP>
 __global__ __launch_bounds__(1024) void k_enc_single(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, int mode)
 {
@@ -75,9 +76,9 @@ __global__ __launch_bounds__(1024) void k_enc_single(const uint8_t *__restrict__
     const int64_t tile = (int64_t)blockDim.x * UPL;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < units; t0 += (int64_t)gridDim.x * tile) {
         if (t0 + tile <= units)
-            enc_step<ALIGNED, UPL, false, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, units, mc);
+            enc_step<AL == 0, UPL, false, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, units, mc, units);
         else
-            enc_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, units, mc);
+            enc_step<AL == 0, UPL, true, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, units, mc, units);
     }
     const int r = (int)(n - 12 * units);
     if (r && blockIdx.x == 0 && threadIdx.x == 0)
@@ -111,7 +112,8 @@ static __device__ __align__(256) VerdictCell g_cells[VERDICT_CELLS];
 //     finishes last writes the verdict (length, -1) or (-1, index) to
 //     d_len / d_err and returns the cell to rest. The cell must be at rest at
 //     launch and used by no other launch until this one ends.
-template <bool ALIGNED, int UPL, int MAP, bool CELL>
+// AL as for k_enc_single.
+template <int AL, int UPL, int MAP, bool CELL>
 __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__ src, int64_t n,
                                                      uint8_t *__restrict__ dst, int mode,
                                                      unsigned long long *err_slot, int64_t *len_slot,
@@ -130,9 +132,9 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
     const int64_t tile = (int64_t)blockDim.x * UPL;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < L; t0 += (int64_t)gridDim.x * tile) {
         if (t0 + tile <= L)
-            dec_step<ALIGNED, UPL, false, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es);
+            dec_step<AL == 0, UPL, false, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es, L);
         else
-            dec_step<ALIGNED, UPL, true, MAP>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es);
+            dec_step<AL == 0, UPL, true, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es, L);
     }
     int64_t len = -1;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
@@ -312,7 +314,7 @@ int single_grid(int dir, int64_t units, int *block, int *upl, int *grid)
     default: hipLaunchKernelGGL((KERN<A, 4, M>), grid, block, 0, s, __VA_ARGS__); break;         \
     }
 
-template <bool A>
+template <int A>
 void launch_enc_single(int upl, int map, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
                        int mode, hipStream_t s)
 {
@@ -333,7 +335,7 @@ void launch_enc_single(int upl, int map, int grid, int block, const uint8_t *src
     default: hipLaunchKernelGGL((k_dec_single<A, 4, M, C>), grid, block, 0, s, __VA_ARGS__); break; \
     }
 
-template <bool A, bool C>
+template <int A, bool C>
 void launch_dec_single(int upl, int map, int grid, int block, const uint8_t *src, int64_t n, uint8_t *dst,
                        int mode, unsigned long long *slot, int64_t *len_slot, VerdictCell *cell,
                        int64_t *d_len, int64_t *d_err, hipStream_t s)
@@ -352,6 +354,12 @@ bool aligned4(const void *a, const void *b)
     return (((uintptr_t)a | (uintptr_t)b) & 3) == 0;
 }
 
+// Alignment class of a single-buffer launch (the AL template argument).
+int align_class(const void *src, const void *dst)
+{
+    return aligned4(src, dst) ? 0 : ((uintptr_t)dst & 3) == 0 ? 1 : 2;
+}
+
 }  // namespace
 
 int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, hipStream_t s)
@@ -360,8 +368,11 @@ int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, h
     int rc = single_grid(0, n / 12, &block, &upl, &grid);
     if (rc) return rc;
     const int map = g_single[0].map.load();
-    if (aligned4(src, dst)) launch_enc_single<true>(upl, map, grid, block, src, n, dst, mode, s);
-    else launch_enc_single<false>(upl, map, grid, block, src, n, dst, mode, s);
+    switch (align_class(src, dst)) {
+    case 0: launch_enc_single<0>(upl, map, grid, block, src, n, dst, mode, s); break;
+    case 1: launch_enc_single<1>(upl, map, grid, block, src, n, dst, mode, s); break;
+    default: launch_enc_single<2>(upl, map, grid, block, src, n, dst, mode, s); break;
+    }
     LAUNCH_TRY();
     return B64_OK;
 }
@@ -375,12 +386,20 @@ int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, u
     int rc = single_grid(1, (n - 1) / 16, &block, &upl, &grid);
     if (rc) return rc;
     const int map = g_single[1].map.load();
-    if (aligned4(src, dst))
-        launch_dec_single<true, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr,
-                                       nullptr, nullptr, s);
-    else
-        launch_dec_single<false, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr,
-                                        nullptr, nullptr, s);
+    switch (align_class(src, dst)) {
+    case 0:
+        launch_dec_single<0, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr, nullptr,
+                                    nullptr, s);
+        break;
+    case 1:
+        launch_dec_single<1, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr, nullptr,
+                                    nullptr, s);
+        break;
+    default:
+        launch_dec_single<2, false>(upl, map, grid, block, src, n, dst, mode, slot, len_slot, nullptr, nullptr,
+                                    nullptr, s);
+        break;
+    }
     LAUNCH_TRY();
     return B64_OK;
 }
@@ -498,12 +517,20 @@ int decode_with_verdict(const uint8_t *src, int64_t n, uint8_t *dst, int mode, i
         }
         if (grid <= CELL_MAX_BLOCKS) {
             const int map = g_single[1].map.load();
-            if (aligned4(src, dst))
-                launch_dec_single<true, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell,
-                                              d_len, d_err, s);
-            else
-                launch_dec_single<false, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell,
-                                               d_len, d_err, s);
+            switch (align_class(src, dst)) {
+            case 0:
+                launch_dec_single<0, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, d_len,
+                                           d_err, s);
+                break;
+            case 1:
+                launch_dec_single<1, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, d_len,
+                                           d_err, s);
+                break;
+            default:
+                launch_dec_single<2, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, d_len,
+                                           d_err, s);
+                break;
+            }
             LAUNCH_TRY();
             return B64_OK;
         }

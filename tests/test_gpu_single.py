@@ -224,6 +224,48 @@ def test_misaligned_subbuffers(soff, doff):
         assert np.all(dbh[:doff] == 0xCD) and np.all(dbh[doff + n:] == 0xCD)
 
 
+# (block, units per lane, blocks per CU; -1 = one workgroup per tile)
+SPLIT_SHAPES = [(256, 2, -1), (64, 1, -1), (1024, 8, -1), (512, 4, 1), (128, 2, 3)]
+
+
+@pytest.mark.parametrize("shape", SPLIT_SHAPES, ids=[f"{b}x{u}_g{g}" for b, u, g in SPLIT_SHAPES])
+def test_misaligned_destination_whole_dword_runs(shape):
+    """A destination that is not 4-byte aligned is written in whole dwords per
+    wave, each wave rebuilding the last word of the unit before its own: every
+    launch shape (one-shot and grid-stride, guarded last tiles), every
+    character map, sizes around the tile edges, against the oracle, with
+    guard bytes on both sides of the output."""
+    b, u, g = shape
+    try:
+        for n in [13, 12 * 64 + 1, 12 * 64 * 5 + 11, 100_003, 1_000_001]:
+            x = rnd(n, n + b)
+            t = oracle.encode(x)
+            m = t.size
+            for doff in (1, 2, 3):
+                for char_map in (0, 1, 2):
+                    codec.set_single_tune(0, b, u, g, char_map)
+                    outbig = torch.full((m + 16,), 0xAB, dtype=torch.uint8, device=DEV)
+                    codec.encode(dev(x), out=outbig[doff:doff + m])
+                    ob = host(outbig)
+                    assert np.array_equal(ob[doff:doff + m], t), (n, doff, char_map)
+                    assert np.all(ob[:doff] == 0xAB) and np.all(ob[doff + m:] == 0xAB)
+                for char_map in (0, 1):
+                    codec.set_single_tune(1, b, u, g, char_map)
+                    cap = oracle.decoded_max(m)
+                    db = torch.full((cap + 16,), 0xCD, dtype=torch.uint8, device=DEV)
+                    out, err = codec.decode(dev(t), out=db[doff:doff + cap])
+                    assert err == -1 and np.array_equal(host(out), x), (n, doff, char_map)
+                    dbh = host(db)
+                    assert np.all(dbh[:doff] == 0xCD) and np.all(dbh[doff + n:] == 0xCD)
+                    bad = t.copy()
+                    bad[m // 2] = ord("?")
+                    got, err = codec.decode(dev(bad), out=db[doff:doff + cap])
+                    assert (got, err) == (None, oracle.decode(bad)[1]), (n, doff, char_map)
+    finally:
+        codec.set_single_tune(0, 512, 2, -1, 0)
+        codec.set_single_tune(1, 256, 2, -1, 0)
+
+
 def test_decode_writes_nothing_past_the_decoded_length():
     for n in [1, 2, 4, 5, 100, 1001]:
         x = rnd(n, 99 + n)

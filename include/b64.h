@@ -122,10 +122,11 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
  * cell, one up to 262,160 characters (a single workgroup); three otherwise
  * (slot set-up, decode, verdict). Each device has 1,024 verdict cells, given
  * out to the first 1,024 distinct stream handles that decode on it and kept
- * for the life of the process. Streams being captured into a graph and the
- * per-thread default stream get none. A cell is reused only by later work on
- * the same stream handle: a stream destroyed while its decode still runs
- * must not have its handle reused for a decode before that work ends.
+ * for the life of the process. Streams being captured into a graph, the
+ * per-thread default stream and streams of a device other than the current
+ * one get none. A cell is reused only by later work on the same stream
+ * handle: a stream destroyed while its decode still runs must not have its
+ * handle reused for a decode before that work ends.
  * b64_decode and b64_decode_ex take the same path on their stream. */
 int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, int64_t *d_len,
                      int64_t *d_err, void *stream);

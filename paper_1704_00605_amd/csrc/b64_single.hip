@@ -410,8 +410,9 @@ namespace {
 // run one after another, so a cell is back at rest before the next launch
 // on its stream starts, while launches on different streams never share
 // one. Streams beyond VERDICT_CELLS per device, the per-thread default
-// stream (one handle for many streams) and streams being captured (a graph
-// may be replayed anywhere) get no cell; their decodes take three launches.
+// stream (one handle for many streams), streams being captured (a graph may
+// be replayed anywhere) and streams of a device other than the current one
+// get no cell; their decodes take three launches.
 struct CellTable {
     std::mutex mu;
     int dev = -1;
@@ -434,6 +435,14 @@ VerdictCell *stream_cell(hipStream_t s)
     if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
+    }
+    if (s != nullptr) {  // cells live on the current device: a stream of another takes none
+        hipDevice_t sd;
+        if (hipStreamGetDevice(s, &sd) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (sd != dev) return nullptr;
     }
     CellTable *t = nullptr;
     {

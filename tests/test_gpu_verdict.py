@@ -160,3 +160,26 @@ def test_captured_decode_replays():
             assert tuple(res[k:k + 2].cpu().tolist()) == WANT[i][:2], CASES[i][0]
         assert torch.equal(out[:WANT[i_ok][0]], dev(WANT[i_ok][2]))
         assert torch.equal(out_s[:WANT[i_sok][0]], dev(WANT[i_sok][2]))
+
+
+def test_per_thread_default_stream_takes_no_cell():
+    """The per-thread default stream is one handle for many streams, so it
+    gets no verdict cell: its decodes take the three-launch path (and the
+    one-workgroup kernel below 256 KiB). Every verdict is checked after a
+    device-wide synchronisation."""
+    import ctypes
+    from paper_1704_00605_amd._lib import lib
+    per_thread = ctypes.c_void_p(2)  # hipStreamPerThread
+    torch.cuda.synchronize()
+    jobs = []
+    for i in (0, 1, 8, 9, 10, 5, 0):
+        _, t, a = CASES[i]
+        out = torch.empty(codec.decoded_max(t.size, a & ~0xff) + 16, dtype=torch.uint8, device=DEV)
+        res = torch.full((2,), 12345, dtype=torch.int64, device=DEV)
+        torch.cuda.synchronize()
+        rp = res.data_ptr()
+        rc = lib().b64_decode_async(ctypes.c_void_p(text(i).data_ptr()), t.size, ctypes.c_void_p(out.data_ptr()),
+                                    int(a), ctypes.c_void_p(rp), ctypes.c_void_p(rp + 8), per_thread)
+        assert rc == 0
+        jobs.append((i, out, res))
+    _check(jobs)

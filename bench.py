@@ -666,7 +666,7 @@ def report_serving(seconds, sweep=True):
     if sweep:
         rows = []
         best = None
-        for rate in (200_000, 400_000, 800_000, 1_600_000, 3_200_000, 6_400_000):
+        for rate in (200_000, 400_000, 800_000, 1_600_000, 3_200_000, 6_400_000, 12_800_000, 25_600_000):
             progress(f"serving sweep: {rate} requests/s")
             trr = workloads.serving_trace(rate=float(rate), seconds=1.0, seed=4)
             rq = serve.build_requests(trr, banks, seed=41)

@@ -11,10 +11,8 @@
 #include <chrono>
 #include <deque>
 #include <mutex>
-#include <set>
 #include <string>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "b64.h"
@@ -153,16 +151,70 @@ int b64_graph_destroy(b64_graph *g)
 // Buddy allocator over [0, capacity): the capacity (rounded down to the
 // minimum block) is split into power-of-two top blocks in descending size,
 // so every block is aligned to its own size and its buddy is offset ^ size.
+// An allocation takes the lowest free block of the smallest level that has
+// one. Bookkeeping is O(1) per level: for each level a bit tree of its free
+// blocks (leaf bits plus summary words, so the lowest free block is a few
+// find-first-set steps away) and a count; for every minimum block a byte
+// with the level + 1 of the live block that starts there. Tree containers
+// had cost about 340 ns per allocation and release, which capped the
+// serving loop near 3 million requests per second.
+namespace {
+
+// Set of indexes [0, n) with O(log64 n) insert, erase and lowest member.
+struct BitTree {
+    std::vector<std::vector<uint64_t>> lv;  // lv[0]: members; lv[i + 1]: non-zero words of lv[i]
+
+    void init(int64_t n)
+    {
+        lv.clear();
+        int64_t bits = n;
+        do {
+            const int64_t words = (bits + 63) / 64;
+            lv.emplace_back((size_t)words, 0ull);
+            bits = words;
+        } while (bits > 1);
+    }
+    bool test(int64_t i) const { return (lv[0][(size_t)(i >> 6)] >> (i & 63)) & 1; }
+    void insert(int64_t i)
+    {
+        for (auto &w : lv) {
+            const bool was = w[(size_t)(i >> 6)] != 0;
+            w[(size_t)(i >> 6)] |= 1ull << (i & 63);
+            if (was) return;  // the summaries above already mark this word
+            i >>= 6;
+        }
+    }
+    void erase(int64_t i)
+    {
+        for (auto &w : lv) {
+            w[(size_t)(i >> 6)] &= ~(1ull << (i & 63));
+            if (w[(size_t)(i >> 6)] != 0) return;  // the word still has members
+            i >>= 6;
+        }
+    }
+    int64_t lowest() const  // -1 when empty
+    {
+        if (lv.back()[0] == 0) return -1;
+        int64_t i = 0;
+        for (size_t l = lv.size(); l-- > 0;) i = i * 64 + __builtin_ctzll(lv[l][(size_t)i]);
+        return i;
+    }
+};
+
+}  // namespace
+
 struct b64_pool {
     std::mutex mu;
     int64_t minb = 256;
+    int lgminb = 8;
     int64_t capacity = 0;
     int64_t used = 0;
     int64_t peak = 0;
     int maxk = 0;
-    std::vector<std::set<int64_t>> free_by_k;      // k -> offsets of free blocks of size minb << k
-    std::unordered_map<int64_t, int> live;         // offset -> k
-    std::vector<std::pair<int64_t, int>> tops;     // (offset, k) of top blocks
+    std::vector<BitTree> free_k;              // k -> free blocks of size minb << k (index = offset >> (lgminb + k))
+    std::vector<int64_t> nfree;               // k -> number of free blocks
+    std::vector<uint8_t> live;                // minimum block index -> 1 + level of the live block starting there, or 0
+    std::vector<std::pair<int64_t, int>> tops;  // (offset, k) of top blocks
 };
 
 namespace {
@@ -181,6 +233,18 @@ int top_k_of(const b64_pool *p, int64_t off)
     return -1;
 }
 
+void pool_put(b64_pool *p, int k, int64_t off)
+{
+    p->free_k[k].insert(off >> (p->lgminb + k));
+    p->nfree[k]++;
+}
+
+void pool_take(b64_pool *p, int k, int64_t off)
+{
+    p->free_k[k].erase(off >> (p->lgminb + k));
+    p->nfree[k]--;
+}
+
 }  // namespace
 
 extern "C" {
@@ -190,22 +254,23 @@ int b64_pool_create(int64_t capacity, int64_t min_block, b64_pool **out)
     if (!out || capacity <= 0) return b64i_fail(B64_BAD_ARG, "bad pool capacity");
     if (min_block <= 0) min_block = 256;
     if (min_block & (min_block - 1)) return b64i_fail(B64_BAD_ARG, "min_block must be a power of two");
+    int64_t units = capacity / min_block;
+    if (units <= 0) return b64i_fail(B64_BAD_ARG, "pool capacity below one block");
     auto *p = new b64_pool();
     p->minb = min_block;
-    int64_t units = capacity / min_block;
-    if (units <= 0) {
-        delete p;
-        return b64i_fail(B64_BAD_ARG, "pool capacity below one block");
-    }
+    p->lgminb = ceil_log2(min_block);
     p->capacity = units * min_block;
     p->maxk = 0;
     while (((int64_t)1 << (p->maxk + 1)) <= units) p->maxk++;
-    p->free_by_k.resize(p->maxk + 1);
+    p->free_k.resize(p->maxk + 1);
+    p->nfree.assign(p->maxk + 1, 0);
+    for (int k = 0; k <= p->maxk; k++) p->free_k[k].init((units >> k) + 1);
+    p->live.assign((size_t)units, 0);
     int64_t off = 0;
     for (int k = p->maxk; k >= 0; k--) {
         if (units & ((int64_t)1 << k)) {
             p->tops.push_back({off, k});
-            p->free_by_k[k].insert(off);
+            pool_put(p, k, off);
             off += min_block << k;
         }
     }
@@ -217,19 +282,20 @@ int b64_pool_alloc(b64_pool *p, int64_t bytes, int64_t *offset)
 {
     if (!p || !offset || bytes < 0) return b64i_fail(B64_BAD_ARG, "bad pool allocation");
     if (bytes == 0) bytes = 1;
+    if (bytes > p->capacity) return B64_POOL_FULL;
     const int k = ceil_log2((bytes + p->minb - 1) / p->minb);
     std::lock_guard<std::mutex> lk(p->mu);
     if (k > p->maxk) return B64_POOL_FULL;
     int j = k;
-    while (j <= p->maxk && p->free_by_k[j].empty()) j++;
+    while (j <= p->maxk && p->nfree[j] == 0) j++;
     if (j > p->maxk) return B64_POOL_FULL;
-    int64_t off = *p->free_by_k[j].begin();
-    p->free_by_k[j].erase(p->free_by_k[j].begin());
+    const int64_t off = p->free_k[j].lowest() << (p->lgminb + j);
+    pool_take(p, j, off);
     while (j > k) {  // split, keep the lower half
         j--;
-        p->free_by_k[j].insert(off + (p->minb << j));
+        pool_put(p, j, off + (p->minb << j));
     }
-    p->live[off] = k;
+    p->live[(size_t)(off >> p->lgminb)] = (uint8_t)(k + 1);
     p->used += p->minb << k;
     p->peak = std::max(p->peak, p->used);
     *offset = off;
@@ -240,23 +306,21 @@ int b64_pool_free(b64_pool *p, int64_t offset)
 {
     if (!p) return b64i_fail(B64_BAD_ARG, "null pool");
     std::lock_guard<std::mutex> lk(p->mu);
-    auto it = p->live.find(offset);
-    if (it == p->live.end()) return b64i_fail(B64_BAD_ARG, "offset is not a live pool block");
-    int k = it->second;
-    p->live.erase(it);
+    if (offset < 0 || offset >= p->capacity || (offset & (p->minb - 1)) || p->live[(size_t)(offset >> p->lgminb)] == 0)
+        return b64i_fail(B64_BAD_ARG, "offset is not a live pool block");
+    int k = p->live[(size_t)(offset >> p->lgminb)] - 1;
+    p->live[(size_t)(offset >> p->lgminb)] = 0;
     p->used -= p->minb << k;
     const int topk = top_k_of(p, offset);
     int64_t off = offset;
     while (k < topk) {  // merge with a free buddy
-        const int64_t size = p->minb << k;
-        const int64_t buddy = off ^ size;
-        auto f = p->free_by_k[k].find(buddy);
-        if (f == p->free_by_k[k].end()) break;
-        p->free_by_k[k].erase(f);
+        const int64_t buddy = off ^ (p->minb << k);
+        if (!p->free_k[k].test(buddy >> (p->lgminb + k))) break;
+        pool_take(p, k, buddy);
         off = std::min(off, buddy);
         k++;
     }
-    p->free_by_k[k].insert(off);
+    pool_put(p, k, off);
     return B64_OK;
 }
 

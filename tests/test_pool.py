@@ -85,3 +85,79 @@ def test_eight_gib_pool_peak_tracking():
     for o in offs:
         p.free(o)
     assert p.free_bytes() == 8 << 30
+
+
+class _ModelBuddy:
+    """Plain buddy allocator with sorted free lists: the lowest free block of
+    the smallest size that has one, split keeping the lower half, merged with
+    a free buddy inside its top block on release."""
+
+    def __init__(self, capacity, minb):
+        self.minb = minb
+        units = capacity // minb
+        self.maxk = units.bit_length() - 1
+        self.free = {k: set() for k in range(self.maxk + 1)}
+        self.live = {}
+        self.tops = []
+        off = 0
+        for k in range(self.maxk, -1, -1):
+            if units & (1 << k):
+                self.tops.append((off, k))
+                self.free[k].add(off)
+                off += minb << k
+
+    def alloc(self, n):
+        n = max(n, 1)
+        k = 0
+        while (self.minb << k) < n:
+            k += 1
+        if k > self.maxk:
+            return None
+        j = next((j for j in range(k, self.maxk + 1) if self.free[j]), None)
+        if j is None:
+            return None
+        off = min(self.free[j])
+        self.free[j].remove(off)
+        while j > k:
+            j -= 1
+            self.free[j].add(off + (self.minb << j))
+        self.live[off] = k
+        return off
+
+    def release(self, off):
+        k = self.live.pop(off)
+        topk = next(t for o, t in self.tops if o <= off < o + (self.minb << t))
+        while k < topk:
+            buddy = off ^ (self.minb << k)
+            if buddy not in self.free[k]:
+                break
+            self.free[k].remove(buddy)
+            off = min(off, buddy)
+            k += 1
+        self.free[k].add(off)
+
+
+@pytest.mark.parametrize("capacity,minb", [((64 << 20) + (3 << 16) + 768, 256), (1 << 24, 4096)])
+def test_same_offsets_as_a_plain_buddy_model(capacity, minb):
+    """20,000 random allocations and releases (sizes log-uniform from 1 byte
+    to the pool's capacity): every returned offset, every refusal and the
+    free byte count equal those of a plain model of the same policy."""
+    rng = np.random.default_rng(7)
+    p = BuddyPool(capacity, minb)
+    m = _ModelBuddy(capacity, minb)
+    live = []
+    for _ in range(20000):
+        if live and rng.uniform() < 0.48:
+            off = live.pop(int(rng.integers(0, len(live))))
+            p.free(off)
+            m.release(off)
+        else:
+            n = int(np.exp(rng.uniform(0, np.log(capacity))))
+            got, want = p.try_alloc(n), m.alloc(n)
+            assert got == want, n
+            if got is not None:
+                live.append(got)
+        assert p.free_bytes() == capacity // minb * minb - sum(minb << k for k in m.live.values())
+    for off in live:
+        p.free(off)
+    assert p.free_bytes() == capacity // minb * minb

@@ -2,7 +2,9 @@
 //
 //   k_plan_reduce / k_plan_scan   device planning: per-message unit counts ->
 //                                 exclusive scan (unit_off), output-length
-//                                 and error-slot init.
+//                                 and error-slot init. A decode's verdict
+//                                 slots are final when its codec kernel
+//                                 ends (see msg_error).
 //   k_enc_batch_t / k_dec_batch_t persistent codec, tile layout: tiles of
 //                                 the flattened unit space of all messages,
 //                                 grid-stride.
@@ -13,7 +15,7 @@
 //                                 16-byte chunks into LDS, its messages found
 //                                 from a tile table filled by the planning
 //                                 pass.
-//   k_dec_batch_final             per-message verdicts.
+//   k_each_final                  verdicts of the per-message baseline.
 //   k_out_reduce / k_out_scan     exclusive scan of output sizes.
 #include <hip/hip_runtime.h>
 
@@ -127,7 +129,7 @@ struct TileTab {
 
 // unit_off = exclusive scan of units per message (N + 1 entries), plus
 // per-message initialisation: encode out_len (known from the length);
-// decode out_len = 0 and err_off = ERR_NONE (the atomicMin sentinel); and
+// decode out_len = 0 and err_off = -1 (see msg_error); and
 // the tile table entries of the tiles whose first unit lies in the message.
 template <int DIR>
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
                 out_len[i] = enc_len_of(len, fl & M_NOPAD);
             } else {
                 out_len[i] = 0;
-                err_off[i] = (int64_t)ERR_NONE;
+                err_off[i] = -1;
             }
         }
         s += u[k];
@@ -283,10 +285,29 @@ __device__ __forceinline__ void enc_batch_unit(const uint8_t *__restrict__ src, 
     }
 }
 
+// Verdict slots of a batched decode, formed in place: the plan sets
+// out_len = 0 and err_off = -1, which as an unsigned value is above every
+// index, so atomicMin keeps the first offending index and -1 stays where
+// there is none. A unit that finds an error also sets out_len to -1; the
+// final unit of a valid message moves out_len from 0 to its length, which
+// fails once an error has set -1, and a later error overwrites the length.
+// So the slots hold the verdict when the codec kernel ends, whatever order
+// the units ran in.
+__device__ __forceinline__ void msg_error(int64_t *__restrict__ out_len, int64_t *__restrict__ err_off, int64_t i,
+                                          int64_t pos)
+{
+    atomicMin((unsigned long long *)&err_off[i], (unsigned long long)pos);
+    atomicExch((unsigned long long *)&out_len[i], ~0ull);
+}
+
+__device__ __forceinline__ void msg_length(int64_t *__restrict__ out_len, int64_t i, int64_t len)
+{
+    atomicCAS((unsigned long long *)&out_len[i], 0ull, (unsigned long long)len);
+}
+
 // One unit of the batched decode: interior units (16 characters, none of
 // them the message's last) or the final unit with the padding and length
-// rules. Errors lower the message's err_off; the final unit's lane writes
-// the decoded length when that unit is valid.
+// rules, reported through msg_error / msg_length.
 __device__ __forceinline__ void dec_batch_unit(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
                                                const LaneRef &r, bool interior, const uint32_t (&w)[4],
                                                const uint8_t *tabs, int64_t *__restrict__ out_len,
@@ -298,16 +319,12 @@ __device__ __forceinline__ void dec_batch_unit(const uint8_t *__restrict__ src, 
         uint32_t o[3];
         const uint32_t bad = dec_unit(w[0], w[1], w[2], w[3], tab, o[0], o[1], o[2]);
         store_words<3, true>(q, o);
-        if (bad & INVALID) {
-            const int64_t pos = 16 * r.j + dec_first_bad(w[0], w[1], w[2], w[3], tab);
-            atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)pos);
-        }
+        if (bad & INVALID)
+            msg_error(out_len, err_off, r.mm, 16 * r.j + dec_first_bad(w[0], w[1], w[2], w[3], tab));
     } else {
         const int res = dec_tail_inl(src + r.b + 16 * r.j, (int)(r.n - 16 * r.j), r.n, q, tab, r.fl);
-        if (res >= 0)
-            atomicMin((unsigned long long *)&err_off[r.mm], (unsigned long long)(16 * r.j + res));
-        else
-            out_len[r.mm] = 12 * r.j + (-1 - res);
+        if (res >= 0) msg_error(out_len, err_off, r.mm, 16 * r.j + res);
+        else msg_length(out_len, r.mm, 12 * r.j + (-1 - res));
     }
 }
 
@@ -494,15 +511,16 @@ __global__ __launch_bounds__(1024) void k_dec_batch_w(
             uint8_t *q = dst + c.o;
             const MapCtx mc{(const uint8_t *)s_tab + 256 * (c.fl & M_URL)};
             unsigned long long *slot = (unsigned long long *)&err_off[c.m];
+            int64_t *lslot = &out_len[c.m];
             const int64_t first = gs - c.u0 + __lane_id();
             const bool al = (((uintptr_t)p | (uintptr_t)q) & 3) == 0;
             if (inside >= UPL && g + UPL <= g1) {
-                if (al) dec_step<true, UPL, false>(p, q, first, 64, 0, mc, slot);
-                else dec_step<false, UPL, false>(p, q, first, 64, 0, mc, slot);
+                if (al) dec_step<true, UPL, false>(p, q, first, 64, 0, mc, slot, 0, lslot);
+                else dec_step<false, UPL, false>(p, q, first, 64, 0, mc, slot, 0, lslot);
                 g += UPL;
             } else {
-                if (al) dec_step<true, 1, false>(p, q, first, 64, 0, mc, slot);
-                else dec_step<false, 1, false>(p, q, first, 64, 0, mc, slot);
+                if (al) dec_step<true, 1, false>(p, q, first, 64, 0, mc, slot, 0, lslot);
+                else dec_step<false, 1, false>(p, q, first, 64, 0, mc, slot, 0, lslot);
                 g += 1;
             }
             continue;
@@ -633,14 +651,15 @@ __global__ __launch_bounds__(1024) void k_dec_batch_t(
         const int fl = flags ? flags[m] : 0;
         const MapCtx tab{tabs + 256 * (fl & M_URL)};
         unsigned long long *slot = (unsigned long long *)&err_off[m];
+        int64_t *lslot = &out_len[m];
         const int64_t j0 = t0 - u0, j1 = t1 - u0;
         const bool whole = t1 - t0 == (int64_t)blockDim.x * UPL;
         if ((((uintptr_t)p | (uintptr_t)q) & 3) == 0) {
-            if (whole) dec_step<true, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
-            else dec_step<true, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
+            if (whole) dec_step<true, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot, 0, lslot);
+            else dec_step<true, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot, 0, lslot);
         } else {
-            if (whole) dec_step<false, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
-            else dec_step<false, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot);
+            if (whole) dec_step<false, UPL, false>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot, 0, lslot);
+            else dec_step<false, UPL, true>(p, q, j0 + threadIdx.x, blockDim.x, j1, tab, slot, 0, lslot);
         }
     };
     auto general = [&](int64_t m0, int64_t u) {
@@ -844,23 +863,22 @@ __global__ __launch_bounds__(S_BLOCK) void k_batch_s(
                     uint32_t oc[3];
                     const uint32_t bad = dec_unit(w[0], w[1], w[2], w[3], tab, oc[0], oc[1], oc[2]);
                     store_words<3, true>(q, oc);
-                    if (bad & INVALID) {
-                        const int64_t pos = 16 * j + dec_first_bad(w[0], w[1], w[2], w[3], tab);
-                        atomicMin((unsigned long long *)&err_off[mi], (unsigned long long)pos);
-                    }
+                    if (bad & INVALID)
+                        msg_error(out_len, err_off, mi, 16 * j + dec_first_bad(w[0], w[1], w[2], w[3], tab));
                 } else {
                     const int res = dec_tail_fast(w, (int)(n - 16 * j), n, q, tab, fl);
-                    if (res >= 0)
-                        atomicMin((unsigned long long *)&err_off[mi], (unsigned long long)(16 * j + res));
-                    else
-                        out_len[mi] = 12 * j + (-1 - res);
+                    if (res >= 0) msg_error(out_len, err_off, mi, 16 * j + res);
+                    else msg_length(out_len, mi, 12 * j + (-1 - res));
                 }
             }
         }
     }
 }
 
-__global__ void k_dec_batch_final(int64_t N, int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
+// Verdicts of the per-message decodes (b64_decode_each), which report like
+// single-buffer decodes: an ERR_NONE error slot becomes -1, any other marks
+// the length -1.
+__global__ void k_each_final(int64_t N, int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -1112,9 +1130,6 @@ int launch_dec_batch(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
         B64_LAUNCH_UPL(k_dec_batch_t, upl, src, msgs, N, dst, out_off, flags, unit_off, out_len, err_off);
     }
     LAUNCH_TRY();
-    const int fb = (int)std::min<int64_t>((N + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_dec_batch_final, fb, 256, 0, s, N, out_len, err_off);
-    LAUNCH_TRY();
     return B64_OK;
 }
 
@@ -1314,7 +1329,7 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
                                 (unsigned long long *)(err_off + i), out_len + i, s);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_dec_batch_final, fb, 256, 0, s, N, out_len, err_off);
+    hipLaunchKernelGGL(k_each_final, fb, 256, 0, s, N, out_len, err_off);
     LAUNCH_TRY();
     return B64_OK;
 }

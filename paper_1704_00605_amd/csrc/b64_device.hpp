@@ -707,11 +707,12 @@ __device__ __forceinline__ void enc_step(const uint8_t *__restrict__ src, uint8_
 // One grid-stride step of the decode over one buffer (see enc_step for the
 // guard, SPLIT and cover_end). Lanes of a wave hold consecutive units, so the
 // lowest erring lane of a ballot has the wave's smallest offset; it alone
-// performs the atomicMin.
+// performs the atomicMin (and, with bad_len, sets that length slot to -1).
 template <bool ALIGNED, int UPL, bool GUARD, int MAP = 0, bool SPLIT = false>
 __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
                                          int64_t first, int stride, int64_t L, const MapCtx &mc,
-                                         unsigned long long *err_slot, int64_t cover_end = 0)
+                                         unsigned long long *err_slot, int64_t cover_end = 0,
+                                         int64_t *bad_len = nullptr)
 {
     static_assert(!(ALIGNED && SPLIT), "a split store needs a misaligned destination");
     uint32_t w[UPL][4];
@@ -781,6 +782,7 @@ __device__ __forceinline__ void dec_step(const uint8_t *__restrict__ src, uint8_
             if (ball && __lane_id() == __ffsll((long long)ball) - 1) {
                 const int64_t pos = 16 * u + dec_first_bad(w[k][0], w[k][1], w[k][2], w[k][3], mc.tab);
                 atomicMin(err_slot, (unsigned long long)pos);
+                if (bad_len) atomicExch((unsigned long long *)bad_len, ~0ull);
             }
         }
     }

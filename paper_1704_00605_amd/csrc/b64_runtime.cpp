@@ -472,7 +472,7 @@ extern "C" int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const dou
             h[L.unit_off() + i] = u;
             u += dir == B64_DIR_ENCODE ? (in_len[r] + 11) / 12 : (in_len[r] + 15) / 16;
             h[L.out_len() + i] = 0;
-            h[L.err_off() + i] = B64I_ERR_NONE;
+            h[L.err_off() + i] = -1;
             hf[i] = flags ? flags[r] : 0;
         }
         h[L.unit_off() + n] = u;

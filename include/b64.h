@@ -119,8 +119,8 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
  * runtime error code.
  * Launches: one for inputs up to 32 MiB of text on a stream that holds a
  * verdict cell (the last workgroup to finish forms the verdict); without a
- * cell, one up to 262,160 characters (a single workgroup); three otherwise
- * (slot set-up, decode, verdict). Each device has 1,024 verdict cells, given
+ * cell, one up to 262,160 characters (a single workgroup); two otherwise
+ * (slot set-up, decode). Each device has 1,024 verdict cells, given
  * out to the first 1,024 distinct stream handles that decode on it and kept
  * for the life of the process. Streams being captured into a graph, the
  * per-thread default stream and streams of a device other than the current

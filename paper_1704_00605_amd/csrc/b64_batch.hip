@@ -15,7 +15,6 @@
 //                                 16-byte chunks into LDS, its messages found
 //                                 from a tile table filled by the planning
 //                                 pass.
-//   k_each_final                  verdicts of the per-message baseline.
 //   k_out_reduce / k_out_scan     exclusive scan of output sizes.
 #include <hip/hip_runtime.h>
 
@@ -875,19 +874,6 @@ __global__ __launch_bounds__(S_BLOCK) void k_batch_s(
     }
 }
 
-// Verdicts of the per-message decodes (b64_decode_each), which report like
-// single-buffer decodes: an ERR_NONE error slot becomes -1, any other marks
-// the length -1.
-__global__ void k_each_final(int64_t N, int64_t *__restrict__ out_len, int64_t *__restrict__ err_off)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = err_off[i];
-        if (e == (int64_t)ERR_NONE) err_off[i] = -1;
-        else out_len[i] = -1;
-    }
-}
-
 // Output size of message i for b64_batch_out_offsets: encoded length, or the
 // decode slot (capacity rounded up to a multiple of 4).
 __device__ __forceinline__ int64_t out_size_of(int dir, Msgs msgs, const uint8_t *flags, int64_t i)
@@ -1170,9 +1156,9 @@ int decode_batch_any(const uint8_t *src, Msgs msgs, int64_t N, uint8_t *dst, con
 }  // namespace
 
 // Planned batch launches for the serving runtime: the caller supplies the
-// unit prefix (and, for decode, out_len = 0 / err_off = ERR_NONE) computed on
+// unit prefix (and, for decode, out_len = 0 / err_off = -1) computed on
 // the host and uploaded together with the descriptors, so a serving batch is
-// one upload, one codec kernel and (decode) one verdict kernel.
+// one upload and one codec kernel, which leaves the decode verdicts in place.
 int b64i_encode_planned(const uint8_t *src, const int64_t *in_begin, const int64_t *in_len, int64_t N,
                         uint8_t *dst, const int64_t *out_off, const uint8_t *flags,
                         const int64_t *unit_off, const b64_tune *tune, hipStream_t s)
@@ -1303,11 +1289,13 @@ int b64_encode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
     return B64_OK;
 }
 
+// Result slots of the per-message decodes: (0, -1), the verdict of an empty
+// message and the state each single-buffer decode forms its verdict from.
 __global__ void k_each_init(int64_t N, int64_t *__restrict__ d_len, int64_t *__restrict__ d_err)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         d_len[i] = 0;
-        d_err[i] = (int64_t)ERR_NONE;
+        d_err[i] = -1;
     }
 }
 
@@ -1324,13 +1312,11 @@ int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint
     for (int64_t i = 0; i < N; i++) {
         const int64_t n = h_in_off[i + 1] - h_in_off[i];
         const int fl = h_flags ? h_flags[i] : 0;
-        if (n == 0) continue;  // verdict (0, -1) comes from the init and final passes
+        if (n == 0) continue;  // verdict (0, -1) comes from the init pass
         int rc = b64i_enqueue_decode(src + h_in_off[i], n, dst + h_out_off[i], fl & 7,
                                 (unsigned long long *)(err_off + i), out_len + i, s);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_each_final, fb, 256, 0, s, N, out_len, err_off);
-    LAUNCH_TRY();
     return B64_OK;
 }
 

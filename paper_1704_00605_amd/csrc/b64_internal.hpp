@@ -32,9 +32,9 @@ int b64i_parse_mode(int alphabet, int *mode);
 // Encoded length of n bytes under mode bits (with or without padding).
 int64_t b64i_enc_len(int64_t n, int mode);
 
-// Single-buffer launches (enqueue only). Decode needs n >= 1, *err_slot ==
-// ERR_NONE before the kernel; the final unit's lane writes *len_slot when
-// valid, and no verdict is formed.
+// Single-buffer launches (enqueue only). Decode needs n >= 1 and
+// (*len_slot, *err_slot) == (0, -1) before the kernel, which leaves the
+// verdict (length, -1) or (-1, first offending index) in them.
 int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, hipStream_t s);
 int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, unsigned long long *err_slot,
                         int64_t *len_slot, hipStream_t s);

@@ -6,13 +6,16 @@
 //                 16-character units, then the final unit with the padding
 //                 and length rules.
 //   k_dec_small   one-workgroup decode of a short input, verdict included.
-//   k_dec_final   verdict (length, -1) or (-1, first offending index) of a
-//                 decode whose stream has no verdict cell.
+//   k_slots_init  sets a decode's result slots to (0, -1) before the decode
+//                 kernel forms the verdict in them (streams without a cell).
 //
-// A decode's verdict is formed inside k_dec_single itself when its stream
-// holds a verdict cell: the workgroup that finishes last reads the cell
-// (see VerdictCell), so an asynchronous decode is one launch at any size.
-//
+// A decode's verdict is formed inside k_dec_single itself: with a verdict
+// cell, by the workgroup that finishes last (see VerdictCell), so an
+// asynchronous decode is one launch; otherwise in the caller's slots, which
+// k_slots_init has set to (0, -1): an error lowers the error slot (unsigned
+// atomicMin, -1 being above every index) and sets the length to -1, and the
+// valid final unit moves the length from 0 to its value by compare-and-swap.
+
 // Decode errors: a lane whose unit holds a non-symbol computes the exact
 // index; a wave ballot elects the first erring lane, which performs one
 // atomicMin on the 64-bit error slot (Section 2: the decoder must report
@@ -103,10 +106,9 @@ static __device__ __align__(256) VerdictCell g_cells[VERDICT_CELLS];
 // Decode src[0, n), n >= 1. Interior units [0, L) with L = (n - 1) / 16 hold
 // 16 characters that are all before the final one; unit L (1..16 characters)
 // carries the padding and length rules.
-//   CELL == false: err_slot must hold ERR_NONE at launch; it ends holding the
-//     smallest offending index (or ERR_NONE). The lane of the final unit
-//     writes the decoded length to *len_slot when that unit is valid, and
-//     k_dec_final turns the pair into the verdict.
+//   CELL == false: *len_slot and *err_slot must hold 0 and -1 at launch;
+//     they end holding the verdict (length, -1) or (-1, first offending
+//     index).
 //   CELL == true: each workgroup keeps its smallest offending index in LDS,
 //     folds it into *cell and counts itself done there; the workgroup that
 //     finishes last writes the verdict (length, -1) or (-1, index) to
@@ -132,17 +134,24 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
     const int64_t tile = (int64_t)blockDim.x * UPL;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < L; t0 += (int64_t)gridDim.x * tile) {
         if (t0 + tile <= L)
-            dec_step<AL == 0, UPL, false, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es, L);
+            dec_step<AL == 0, UPL, false, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es, L,
+                                                         CELL ? nullptr : len_slot);
         else
-            dec_step<AL == 0, UPL, true, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es, L);
+            dec_step<AL == 0, UPL, true, MAP, AL == 2>(src, dst, t0 + threadIdx.x, blockDim.x, L, mc, es, L,
+                                                        CELL ? nullptr : len_slot);
     }
     int64_t len = -1;
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         const int r = (int)(n - 16 * L);
         const int res = dec_tail(src + 16 * L, r, n, dst + 12 * L, tab, mode);
-        if (res >= 0) atomicMin(es, (unsigned long long)(16 * L + res));
-        else if (CELL) len = 12 * L + (-1 - res);
-        else *len_slot = 12 * L + (-1 - res);
+        if (res >= 0) {
+            atomicMin(es, (unsigned long long)(16 * L + res));
+            if (!CELL) atomicExch((unsigned long long *)len_slot, ~0ull);
+        } else if (CELL) {
+            len = 12 * L + (-1 - res);
+        } else {
+            atomicCAS((unsigned long long *)len_slot, 0ull, (unsigned long long)(12 * L + (-1 - res)));
+        }
     }
     if constexpr (CELL) {
         __syncthreads();
@@ -179,7 +188,7 @@ __global__ __launch_bounds__(1024) void k_dec_single(const uint8_t *__restrict__
 // (unsigned atomicMin) and thread 0 writes (length, -1) or (-1, index) at
 // the end. It takes inputs of at most SMALL_UNITS_CELL interior units (one
 // pass of its 1,024 lanes x 2 units), and up to SMALL_UNITS on a stream
-// without a verdict cell, where the alternative is three launches. Between
+// without a verdict cell, where the alternative is two launches. Between
 // the two, the one-launch grid of k_dec_single is faster (6.1 against
 // 6.4-11.8 us for 64-256 KiB of text on MI355X).
 constexpr int64_t SMALL_UNITS_CELL = 2048;
@@ -219,27 +228,14 @@ __global__ __launch_bounds__(1024) void k_dec_small(const uint8_t *__restrict__ 
     }
 }
 
-// Verdict of a single-buffer decode, run after k_dec_single (without a
-// verdict cell) on the same stream: (length, -1) or (-1, first offending
-// index).
-__global__ void k_dec_final(const unsigned long long *err_slot, const int64_t *len_slot, int64_t *out_len,
-                            int64_t *out_err)
-{
-    if (threadIdx.x == 0) {
-        const unsigned long long e = *err_slot;
-        const int64_t len = *len_slot;
-        if (e == ERR_NONE) { *out_len = len; *out_err = -1; }
-        else { *out_len = -1; *out_err = (int64_t)e; }
-    }
-}
-
-// Prepares an asynchronous decode's device slots: the error slot (which is
-// d_err itself) to ERR_NONE, or the final verdict of an empty input.
-__global__ void k_slots_init(int64_t *d_len, int64_t *d_err, int empty)
+// Sets an asynchronous decode's result slots to (0, -1): the verdict of an
+// empty input, and the state k_dec_single (without a cell) forms its
+// verdict from.
+__global__ void k_slots_init(int64_t *d_len, int64_t *d_err)
 {
     if (threadIdx.x == 0) {
         *d_len = 0;
-        *d_err = empty ? -1 : (int64_t)ERR_NONE;
+        *d_err = -1;
     }
 }
 
@@ -377,8 +373,8 @@ int b64i_enqueue_encode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, h
     return B64_OK;
 }
 
-// Enqueues the decode kernel of src[0, n) (n >= 1); the error slot must hold
-// ERR_NONE. No verdict is formed here (see k_dec_final).
+// Enqueues the decode kernel of src[0, n) (n >= 1) that forms its verdict
+// in *len_slot / *slot, which must hold 0 and -1.
 int b64i_enqueue_decode(const uint8_t *src, int64_t n, uint8_t *dst, int mode, unsigned long long *slot,
                         int64_t *len_slot, hipStream_t s)
 {
@@ -412,7 +408,7 @@ namespace {
 // one. Streams beyond VERDICT_CELLS per device, the per-thread default
 // stream (one handle for many streams), streams being captured (a graph may
 // be replayed anywhere) and streams of a device other than the current one
-// get no cell; their decodes take three launches.
+// get no cell; their decodes take two launches.
 struct CellTable {
     std::mutex mu;
     int dev = -1;
@@ -478,16 +474,12 @@ VerdictCell *stream_cell(hipStream_t s)
 // extra launches.
 constexpr int CELL_MAX_BLOCKS = 512;
 
-int decode_three_launches(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
-                          int64_t *d_err, hipStream_t s)
+int decode_two_launches(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len, int64_t *d_err,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, 0);
+    hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err);
     LAUNCH_TRY();
-    int rc = b64i_enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, d_len, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_dec_final, 1, 64, 0, s, (const unsigned long long *)d_err, d_len, d_len, d_err);
-    LAUNCH_TRY();
-    return B64_OK;
+    return b64i_enqueue_decode(src, n, dst, mode, (unsigned long long *)d_err, d_len, s);
 }
 
 // One-workgroup decode of src[0, n) (n >= 1, at most SMALL_UNITS interior
@@ -508,7 +500,7 @@ int decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t 
 //   - on a stream with a verdict cell, up to 32 MiB of text: one launch of
 //     k_dec_single, which forms the verdict itself;
 //   - otherwise, at most SMALL_UNITS interior units: one workgroup;
-//   - otherwise the slot initialisation, k_dec_single and k_dec_final.
+//   - otherwise the slot initialisation and k_dec_single.
 int decode_with_verdict(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
                         int64_t *d_err, hipStream_t s)
 {
@@ -545,7 +537,7 @@ int decode_with_verdict(const uint8_t *src, int64_t n, uint8_t *dst, int mode, i
         }
     }
     if (units <= SMALL_UNITS) return decode_small(src, n, dst, mode, d_len, d_err, s);
-    return decode_three_launches(src, n, dst, mode, d_len, d_err, s);
+    return decode_two_launches(src, n, dst, mode, d_len, d_err, s);
 }
 
 }  // namespace
@@ -618,7 +610,7 @@ int b64_decode_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabet, 
         return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
-        hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err, 1);
+        hipLaunchKernelGGL(k_slots_init, 1, 64, 0, s, d_len, d_err);
         LAUNCH_TRY();
         return B64_OK;
     }

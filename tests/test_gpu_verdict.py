@@ -4,7 +4,7 @@ offending index) from a per-stream verdict cell and returns the cell to rest.
 Every verdict and every decoded byte is compared with the oracle, over runs
 of back-to-back calls on one stream (each call finds the cell at rest), on
 several streams at once (one cell each), in several launch shapes (one-shot
-and grid-stride grids), and under graph capture (no cell: three launches)."""
+and grid-stride grids), and under graph capture (no cell: two launches)."""
 import numpy as np
 import pytest
 import torch
@@ -43,7 +43,7 @@ def _cases():
     short_len = padded[:262_165]                            # length 1 mod 4: error at n - 1 or earlier
     nopad = oracle.encode_nopad(y, URL)                     # 1,333,335 characters
     big = oracle.encode(rng.integers(0, 256, 5 * (1 << 20) + 7, dtype=np.uint8))
-    # 40 MiB of text: beyond the one-launch grids, three launches on any stream
+    # 40 MiB of text: beyond the one-launch grids, two launches on any stream
     huge = oracle.encode(rng.integers(0, 256, 30 * (1 << 20) + 2, dtype=np.uint8))
     huge[huge.size - 900_000] = ord("!")
     # 100,000 characters (6,249 interior units): one workgroup without a
@@ -134,7 +134,7 @@ def test_default_stream_and_sync_calls():
 
 
 def test_captured_decode_replays():
-    """A stream under capture gets no verdict cell; the captured three-launch
+    """A stream under capture gets no verdict cell; the captured two-launch
     decode is replayed with eager one-launch decodes between the replays."""
     i_bad, i_ok, i_sbad, i_sok = 1, 0, 10, 9
     out = torch.empty(codec.decoded_max(CASES[i_ok][1].size) + 16, dtype=torch.uint8, device=DEV)
@@ -164,7 +164,7 @@ def test_captured_decode_replays():
 
 def test_per_thread_default_stream_takes_no_cell():
     """The per-thread default stream is one handle for many streams, so it
-    gets no verdict cell: its decodes take the three-launch path (and the
+    gets no verdict cell: its decodes take the two-launch path (and the
     one-workgroup kernel below 256 KiB). Every verdict is checked after a
     device-wide synchronisation."""
     import ctypes

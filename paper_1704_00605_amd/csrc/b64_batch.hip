@@ -31,7 +31,7 @@ using namespace b64dev;
 static __constant__ Tables c_tab = make_tables();
 
 constexpr int PLAN_BLOCK = 256;
-constexpr int PLAN_PER_THREAD = 8;
+constexpr int PLAN_PER_THREAD = 2;
 constexpr int PLAN_CHUNK = PLAN_BLOCK * PLAN_PER_THREAD;
 
 __device__ __forceinline__ int64_t units_of(int dir, int64_t len)

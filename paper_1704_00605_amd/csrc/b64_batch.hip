@@ -33,6 +33,11 @@ static __constant__ Tables c_tab = make_tables();
 constexpr int PLAN_BLOCK = 256;
 constexpr int PLAN_PER_THREAD = 2;
 constexpr int PLAN_CHUNK = PLAN_BLOCK * PLAN_PER_THREAD;
+// Up to this many chunks (1,048,576 messages) each chunk of k_plan_scan sums
+// the totals of the chunks before it itself (at most 8 loads per thread, no
+// extra launch); beyond, that sum would grow with the square of the chunk
+// count, so k_plan_top scans the totals first.
+constexpr int64_t PLAN_DIRECT_CHUNKS = 2048;
 
 __device__ __forceinline__ int64_t units_of(int dir, int64_t len)
 {
@@ -126,6 +131,25 @@ struct TileTab {
     int64_t *A, *m;
 };
 
+// One block: exclusive scan of the chunk totals, in place (batches of more
+// than PLAN_DIRECT_CHUNKS chunks).
+__global__ __launch_bounds__(1024) void k_plan_top(int64_t chunks, int64_t *__restrict__ partial)
+{
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < chunks; base += blockDim.x) {
+        const int64_t c = base + threadIdx.x;
+        const int64_t v = c < chunks ? partial[c] : 0;
+        const int64_t ex = block_exclusive_scan(v);
+        const int64_t carry = s_carry;
+        if (c < chunks) partial[c] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) s_carry = carry + ex + v;
+        __syncthreads();
+    }
+}
+
 // unit_off = exclusive scan of units per message (N + 1 entries), plus
 // per-message initialisation: encode out_len (known from the length);
 // decode out_len = 0 and err_off = -1 (see msg_error); and
@@ -134,11 +158,17 @@ template <int DIR>
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_scan(
     Msgs msgs, int64_t N, const uint8_t *__restrict__ flags,
     const int64_t *__restrict__ partial, int64_t *__restrict__ unit_off,
-    int64_t *__restrict__ out_len, int64_t *__restrict__ err_off, TileTab tt)
+    int64_t *__restrict__ out_len, int64_t *__restrict__ err_off, TileTab tt, int scanned)
 {
+    // units before this chunk: partial holds the chunk totals, or (scanned)
+    // their exclusive prefix
     int64_t pre = 0;
-    for (int64_t c = threadIdx.x; c < blockIdx.x; c += blockDim.x) pre += partial[c];
-    pre = block_sum(pre);
+    if (scanned) {
+        pre = partial[blockIdx.x];
+    } else {
+        for (int64_t c = threadIdx.x; c < blockIdx.x; c += blockDim.x) pre += partial[c];
+        pre = block_sum(pre);
+    }
     const int64_t i0 = (int64_t)blockIdx.x * PLAN_CHUNK + threadIdx.x * PLAN_PER_THREAD;
     int64_t u[PLAN_PER_THREAD];
     int64_t s = 0;
@@ -1051,8 +1081,13 @@ int plan(Msgs msgs, int64_t N, const uint8_t *flags, void *ws, int64_t ws_bytes,
     }
     hipLaunchKernelGGL((k_plan_reduce<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, msgs, N, partial);
     LAUNCH_TRY();
+    const int scanned = chunks > PLAN_DIRECT_CHUNKS;
+    if (scanned) {
+        hipLaunchKernelGGL(k_plan_top, 1, 1024, 0, s, chunks, partial);
+        LAUNCH_TRY();
+    }
     hipLaunchKernelGGL((k_plan_scan<DIR>), (unsigned)chunks, PLAN_BLOCK, 0, s, msgs, N, flags, partial,
-                       *unit_off, out_len, err_off, *tt);
+                       *unit_off, out_len, err_off, *tt, scanned);
     LAUNCH_TRY();
     return B64_OK;
 }

@@ -73,6 +73,35 @@ def test_noalloc_decode_equals_workspace_form_two_calls(tune):
             assert np.array_equal(got[0][oo[i]:oo[i] + wl[i]], wd[wo[i]:wo[i] + wl[i]]), (N, i)
 
 
+def test_noalloc_at_its_maximum_batch():
+    """Exactly the largest batch the call accepts (1,048,576 messages of 0-30
+    characters of text, many of them invalid), against the workspace form
+    and the oracle: every length, error offset and decoded byte."""
+    N = _lib.NOALLOC_MAX_MESSAGES
+    rng = np.random.default_rng(5)
+    lens = rng.integers(0, 31, N)
+    toff = np.zeros(N + 1, np.int64)
+    np.cumsum(lens, out=toff[1:])
+    # random symbols: a message is invalid when its length is 1 mod 4 or its
+    # last symbol leaves nonzero bits unused (most of the messages here)
+    symbols = np.frombuffer(b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789+/", np.uint8)
+    text = symbols[rng.integers(0, 64, int(toff[-1]))]
+    flags = np.zeros(N, np.uint8)
+    got = _run(_noalloc, text, toff, flags, None)
+    ref = _run(_with_workspace, text, toff, flags, None)
+    wd, wo, wl, we = oracle.decode_batch(text, toff, flags)
+    assert np.array_equal(got[2], wl) and np.array_equal(got[3], we)
+    assert np.array_equal(ref[2], wl) and np.array_equal(ref[3], we)
+    assert (we >= 0).sum() > N // 10 and (wl > 0).sum() > N // 10
+    ok = wl > 0
+    idx_got = np.repeat(got[1][:-1][ok] - np.concatenate([[0], np.cumsum(wl[ok])[:-1]]), wl[ok]) + \
+        np.arange(wl[ok].sum())
+    idx_want = np.repeat(wo[:-1][ok] - np.concatenate([[0], np.cumsum(wl[ok])[:-1]]), wl[ok]) + \
+        np.arange(wl[ok].sum())
+    assert np.array_equal(got[0][idx_got], wd[idx_want])
+    assert np.array_equal(ref[0][idx_got], wd[idx_want])
+
+
 def test_noalloc_refuses_batches_beyond_its_maximum():
     L = _lib.lib()
     N = _lib.NOALLOC_MAX_MESSAGES + 1

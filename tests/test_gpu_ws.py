@@ -78,6 +78,29 @@ def test_ws_multi_tile_layouts_every_shape(shape):
     check(a)
 
 
+def test_ws_every_dword_keep_pattern():
+    """Each aligned dword of the input keeps the bytes of one of the 16
+    kept/removed patterns, dword i taking pattern (7 i + i // 16) mod 16, so
+    every pattern follows stripped runs of every length mod 4 and sits in
+    every lane and tile position; the removed bytes cycle through space, LF
+    and CR."""
+    rng = np.random.default_rng(9)
+    x = rng.integers(0, 256, 150_000, dtype=np.uint8)
+    text = oracle.encode(x)
+    i = np.arange(2 * text.size // 4 + 64)
+    pat = (7 * i + i // 16) % 16
+    kept = ((pat[:, None] >> np.arange(4)) & 1).astype(bool).ravel()
+    where = np.flatnonzero(kept)[:text.size]
+    a = workloads.WS_BYTES[np.arange(kept.size) % 3].copy()
+    a[where] = text
+    a = a[:where[-1] + 1 + 37]                          # ends inside a dword
+    for shape in ((256, 1), (256, 2), (1024, 2)):
+        codec.set_ws_tune(*shape)
+        w = check(a)
+        assert w[1] == -1 and w[0] == x.size and np.array_equal(w[2], x)
+        check(a, shift=3)                               # dwords of the input no longer aligned
+
+
 def test_ws_long_whitespace_runs_across_tiles():
     # runs longer than any tile: tiles with no kept byte, quads and padding
     # split across such tiles

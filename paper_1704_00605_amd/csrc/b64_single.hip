@@ -297,7 +297,10 @@ int single_grid(int dir, int64_t units, int *block, int *upl, int *grid)
     const int64_t per = (int64_t)(*block) * (*upl);
     int64_t tiles = (units + per - 1) / per;
     const int bpc = g_single[dir].blocks_per_cu.load();
-    int64_t cap = bpc ? (int64_t)cus * bpc : (int64_t)INT32_MAX;
+    // a launch holds fewer than 2^32 work-items; the kernels stride over the
+    // tiles, so a capped grid still covers every unit
+    const int64_t cap = std::min<int64_t>(bpc ? (int64_t)cus * bpc : (int64_t)INT32_MAX,
+                                          (((int64_t)1 << 32) - 1) / *block);
     *grid = (int)std::max<int64_t>(1, std::min(tiles, cap));
     return B64_OK;
 }

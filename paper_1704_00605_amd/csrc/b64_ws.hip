@@ -371,7 +371,7 @@ __device__ __forceinline__ uint32_t quad_bits(uint32_t v)
 template <int BLOCK, int CPL, bool ALIGNED>
 __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ src, int64_t n,
                                                   uint8_t *__restrict__ dst, int alpha,
-                                                  unsigned long long *__restrict__ ws, int64_t T)
+                                                  unsigned long long *__restrict__ ws, int64_t T, int64_t t0)
 {
     constexpr int TILE = BLOCK * 16 * CPL;  // input bytes per tile
     constexpr int NW = BLOCK / 64;
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     lds_fill(s_tab, c_ws.cls[alpha], 256);
     const uint8_t *tab = (const uint8_t *)s_tab;
-    const int64_t t = blockIdx.x;
+    const int64_t t = t0 + blockIdx.x;  // tile (a launch covers tiles [t0, t0 + gridDim.x))
     const int64_t base = t * TILE;
     {
         uint32_t w[CPL][4];
@@ -665,18 +665,26 @@ void launch_count(int chunks, int64_t T, const uint8_t *src, int64_t n, unsigned
     }
 }
 
+// The count pass runs 64-256 lanes per tile of 4-32 KiB (at most n / 64
+// work-items, below 2^32 for any n below 2^38). The decode pass runs a
+// workgroup per tile, which passes 2^32 work-items (the most one launch
+// holds) above 2^36 bytes at one 16-byte chunk per lane; its tiles do not
+// depend on each other, so it is launched in pieces of at most
+// (2^32 - 1) / block tiles.
 template <bool A>
 int launch_ws(int block, int cpl, int64_t T, const uint8_t *src, int64_t n, uint8_t *dst, int alpha,
               unsigned long long *ws, hipStream_t s)
 {
-    const dim3 g((unsigned)T);
     const unsigned G = (unsigned)((T + WS_GROUP - 1) / WS_GROUP);
+    const int64_t piece = (((int64_t)1 << 32) - 1) / block;
 #define B64_WS_CASE(B, C)                                                                      \
     if (block == B && cpl == C) {                                                              \
         launch_count<A>(B * C, T, src, n, ws, s);                                              \
         hipLaunchKernelGGL(k_ws_reduce, G, WS_SCAN_BLOCK, 0, s, ws, T);                        \
         hipLaunchKernelGGL(k_ws_prefix, G, WS_SCAN_BLOCK, 0, s, ws, T);                        \
-        hipLaunchKernelGGL((k_dec_ws<B, C, A>), g, B, 0, s, src, n, dst, alpha, ws, T);        \
+        for (int64_t t0 = 0; t0 < T; t0 += piece)                                              \
+            hipLaunchKernelGGL((k_dec_ws<B, C, A>), dim3((unsigned)std::min(piece, T - t0)), B, \
+                               0, s, src, n, dst, alpha, ws, T, t0);                           \
         return B64_OK;                                                                         \
     }
     B64_WS_CASE(256, 1) B64_WS_CASE(256, 2) B64_WS_CASE(256, 4) B64_WS_CASE(256, 8)

@@ -410,6 +410,58 @@ def test_single_buffer_beyond_4gib():
     assert out is None and err == pos
 
 
+def _chunk_payload(i, size):
+    """Chunk i of a payload generated on the device chunk by chunk (seed 40 + i)."""
+    g = torch.Generator(device=DEV)
+    g.manual_seed(40 + i)
+    return torch.randint(0, 256, (size,), dtype=torch.uint8, device=DEV, generator=g)
+
+
+def _need_device_bytes(b):
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < b:
+        pytest.skip(f"needs {b / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+
+
+def test_launch_shape_beyond_2_32_work_items():
+    """A payload of more than 2^32 encode units (51.5 GB) at 1,024 lanes x 1
+    unit with one workgroup per tile: that grid would hold more than 2^32
+    work-items, more than one launch takes, so it is capped and the kernels
+    stride over the remaining tiles. The decode of the text (also more than
+    2^32 units) gives back every byte of the payload, and windows of the
+    text, last unit included, equal the oracle's encoding of the same
+    bytes."""
+    CH = 3 << 30                                     # payload chunk (a multiple of 3)
+    n = 12 * ((1 << 32) + (1 << 20)) + 7             # 4,296,015,872 units + 7 bytes
+    m = 4 * -(-n // 3)
+    _need_device_bytes(n + m + n + (8 << 30))
+    chunks = [(i, min(CH, n - o)) for i, o in enumerate(range(0, n, CH))]
+    x = torch.empty(n, dtype=torch.uint8, device=DEV)
+    for i, size in chunks:
+        x[i * CH:i * CH + size] = _chunk_payload(i, size)
+    try:
+        for d in (0, 1):
+            codec.set_single_tune(d, 1024, 1, -1, 0)
+        t = codec.encode(x)
+        assert t.numel() == m
+        windows = [0, 3 * (1 << 31), 12 * ((1 << 32) - 5), n - n % 3 - 3 * 4096, n - n % 3 - 3]
+        want = [(a, oracle.encode(host(x[a:min(a + 3 * 4096, n)]))) for a in windows]
+        want.append((n - n % 3, oracle.encode(host(x[n - n % 3:]))))  # the padded final group
+        del x
+        for a, w in want:
+            assert np.array_equal(host(t[4 * a // 3:4 * a // 3 + w.size]), w), a
+        out, err = codec.decode(t)
+        assert err == -1 and out.numel() == n
+        del t
+        for i, size in chunks:
+            assert torch.equal(out[i * CH:i * CH + size], _chunk_payload(i, size)), i
+    finally:
+        codec.set_single_tune(0, 512, 2, -1, 0)
+        codec.set_single_tune(1, 256, 2, -1, 0)
+        torch.cuda.empty_cache()
+
+
 def test_plain_entry_points_on_the_null_stream():
     """b64_encode / b64_decode (Section 2, Algorithms 1 and 2) called through
     ctypes as declared: device buffers, the NULL stream, a host err_off. The

@@ -302,3 +302,56 @@ def test_ws_beyond_4gib():
     out, err = codec.decode_ws(wrapped)
     assert out is None and err == p
     wrapped[p] = keep
+
+
+def _chunk_payload(i, size):
+    """Chunk i of a payload generated on the device chunk by chunk (seed 60 + i)."""
+    g = torch.Generator(device=DEV)
+    g.manual_seed(60 + i)
+    return torch.randint(0, 256, (size,), dtype=torch.uint8, device=DEV, generator=g)
+
+
+def test_ws_decode_pass_beyond_2_32_work_items():
+    """A MIME text of more than 2^36 bytes (76-character CRLF lines) at 256
+    lanes x one 16-byte chunk: one workgroup per 4 KiB tile would put more
+    than 2^32 work-items (more than one launch takes) into the decode pass,
+    so it runs as two launches over the tiles. Every decoded byte equals the
+    payload (generated on the device chunk by chunk); lines at the start,
+    middle and end decode as the oracle decodes them; an invalid byte in
+    the second launch's tiles is reported at its index."""
+    LINE, PL = 78, 57                     # characters per line, payload bytes per line
+    L = (1 << 36) // LINE + 4096          # lines
+    nw, n = LINE * L, PL * L
+    torch.cuda.empty_cache()
+    if torch.cuda.mem_get_info()[0] < nw + n + (8 << 30):
+        pytest.skip("needs about 120 GiB of free device memory")
+    K = 1 << 24                           # lines per chunk
+    wrapped = torch.empty(nw, dtype=torch.uint8, device=DEV)
+    w2 = wrapped.view(L, LINE)
+    for c, l0 in enumerate(range(0, L, K)):
+        k = min(K, L - l0)
+        w2[l0:l0 + k, :76] = codec.encode(_chunk_payload(c, PL * k)).view(k, 76)
+    w2[:, 76] = 13
+    w2[:, 77] = 10
+    try:
+        codec.set_ws_tune(256, 1)
+        out, err = codec.decode_ws(wrapped)
+        assert err == -1 and out.numel() == n
+        for c, l0 in enumerate(range(0, L, K)):
+            k = min(K, L - l0)
+            assert torch.equal(out[PL * l0:PL * (l0 + k)], _chunk_payload(c, PL * k)), c
+        for line in (0, L // 2, L - 3):
+            want = oracle.decode_ws(wrapped[LINE * line:LINE * (line + 3)].cpu().numpy())
+            assert want[:2] == (3 * PL, -1)
+            assert np.array_equal(out[PL * line:PL * (line + 3)].cpu().numpy(), want[2])
+        del out
+        p = LINE * (L - 13) + 5           # a symbol in a tile past the first launch's
+        assert p // 4096 >= ((1 << 32) - 1) // 256
+        wrapped[p] = ord("*")
+        want = oracle.decode_ws(wrapped[LINE * (L - 14):LINE * (L - 11)].cpu().numpy())
+        assert want[:2] == (-1, p - LINE * (L - 14))
+        out, err = codec.decode_ws(wrapped)
+        assert out is None and err == p
+    finally:
+        del wrapped, w2
+        torch.cuda.empty_cache()

@@ -366,7 +366,9 @@ int b64_server_run(const b64_server_cfg *cfg, int64_t nreq, const double *t_arri
 /* Plain per-message form of the batched calls (the baseline the batched
  * kernels are measured against): one single-buffer launch per message, all on
  * `stream`. Offsets and flags are HOST arrays here; out_len / err_off are
- * DEVICE arrays (err_off unused for encode and may be NULL). */
+ * DEVICE arrays (err_off unused for encode and may be NULL). b64_encode_each
+ * copies the lengths from a host buffer of its own and waits for `stream`
+ * before it returns; b64_decode_each returns once its work is enqueued. */
 int b64_encode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,
                     const int64_t *h_out_off, const uint8_t *h_flags, int64_t *out_len, void *stream);
 int b64_decode_each(const uint8_t *src, const int64_t *h_in_off, int64_t N, uint8_t *dst,

@@ -602,6 +602,15 @@ __global__ __launch_bounds__(BLOCK) void k_dec_ws(const uint8_t *__restrict__ sr
     }
 }
 
+// Verdict of an empty input: (0, -1).
+__global__ void k_ws_empty(int64_t *d_len, int64_t *d_err)
+{
+    if (threadIdx.x == 0) {
+        *d_len = 0;
+        *d_err = -1;
+    }
+}
+
 // Verdict: (decoded length, -1) or (-1, first offending original index).
 __global__ void k_dec_ws_final(const unsigned long long *__restrict__ ws, int64_t T, int64_t n,
                                int64_t *__restrict__ d_len, int64_t *__restrict__ d_err)
@@ -752,11 +761,10 @@ int b64_decode_ws_async(const uint8_t *src, int64_t n, uint8_t *dst, int alphabe
     if (n < 0 || n > WS_MAX_N) return b64i_fail(B64_BAD_ARG, "length outside [0, 2^38)");
     if (!d_len || !d_err) return b64i_fail(B64_BAD_ARG, "null result slot");
     hipStream_t s = (hipStream_t)stream;
-    if (n == 0) {
-        const int64_t v[2] = {0, -1};
-        HIP_TRY(hipMemcpyAsync(d_len, &v[0], 8, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(d_err, &v[1], 8, hipMemcpyHostToDevice, s));
-        return hipStreamSynchronize(s) == hipSuccess ? B64_OK : b64i_fail(B64_HIP_ERROR, "stream sync");
+    if (n == 0) {  // verdict (0, -1), enqueued like any other (no host wait, capturable)
+        hipLaunchKernelGGL(k_ws_empty, 1, 64, 0, s, d_len, d_err);
+        LAUNCH_TRY();
+        return B64_OK;
     }
     if (!src || (!dst && n >= 4)) return b64i_fail(B64_BAD_ARG, "null buffer with n > 0");
     if (!workspace || workspace_bytes < b64_decode_ws_workspace_bytes(n))

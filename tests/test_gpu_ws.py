@@ -191,6 +191,45 @@ def test_ws_async_reuses_workspace_and_writes_nothing_past_the_length():
         assert np.array_equal(o[:L], x) and (o[L:] == 0xEE).all()
 
 
+def test_ws_async_captured_in_a_graph():
+    """decode_ws_async enqueues kernels only (an empty input too), so it
+    records into a HIP graph; the graph (an empty input, a valid text and a
+    text with an invalid byte, each with its own workspace) is replayed
+    three times with eager decodes of other texts between the replays, and
+    every replay's verdicts and bytes equal the oracle's."""
+    rng = np.random.default_rng(8)
+    x = rng.integers(0, 256, 300_001, dtype=np.uint8)
+    a, pos = workloads.wrap_lines(oracle.encode(x), 76, b"\r\n")
+    bad = a.copy()
+    bad[pos[123_457]] = ord("*")
+    texts = [np.zeros(0, np.uint8), a, bad]
+    want = [oracle.decode_ws(t) for t in texts]
+    assert [w[:2] for w in want] == [(0, -1), (x.size, -1), (-1, int(pos[123_457]))]
+    srcs = [dev(t) if t.size else torch.zeros(1, dtype=torch.uint8, device=DEV)[:0] for t in texts]
+    outs = [torch.zeros(3 * (t.size // 4) + 4, dtype=torch.uint8, device=DEV) for t in texts]
+    wss = [torch.empty(codec.ws_workspace_bytes(t.size), dtype=torch.uint8, device=DEV) for t in texts]
+    res = torch.zeros(6, dtype=torch.int64, device=DEV)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for k in range(3):
+                codec.decode_ws_async(srcs[k], outs[k], res[2 * k:2 * k + 2], wss[k], stream=s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        res.fill_(7)
+        for o in outs:
+            o.fill_(0)
+        g.replay()
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert tuple(res[2 * k:2 * k + 2].tolist()) == want[k][:2], (r, k)
+        assert np.array_equal(outs[1][:x.size].cpu().numpy(), x)
+        y = rng.integers(0, 256, 5000 + r, dtype=np.uint8)
+        check(workloads.wrap_lines(oracle.encode(y), 64, b"\n")[0])
+
+
 def test_ws_mime_1gib_properties():
     """Full-size MIME text (1 GiB payload, 76-character CRLF lines): the decode
     returns the payload; with one injected byte it reports that byte's

@@ -130,6 +130,55 @@ def test_graph_replays_match_eager(direction):
     g.close()
 
 
+@pytest.mark.parametrize("direction", [E, D])
+def test_graph_update_across_planning_topologies(direction):
+    """A captured batch re-pointed from 3,000 messages to 1,200,000 (whose
+    planning takes one more pass, so the update re-instantiates the graph)
+    and back; every replay against the oracle."""
+    rng = np.random.default_rng(31 + direction)
+
+    def batch(N):
+        lens = rng.integers(0, 30, N)
+        off = np.zeros(N + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        data = rng.integers(0, 256, int(off[-1]), dtype=np.uint8)
+        if direction == D:
+            data, off, _ = oracle.encode_batch(data, off)
+            data = data.copy()
+            hit = rng.choice(N, N // 100, replace=False)
+            hit = hit[np.diff(off)[hit] > 0]
+            data[off[hit]] = ord("#")
+        src, in_off = dev(data), dev(off)
+        out_off = codec.batch_out_offsets(direction, in_off)
+        dst = torch.zeros(int(out_off[-1].item()) + 1, dtype=torch.uint8, device=DEV)
+        ol = torch.full((N,), -7, dtype=torch.int64, device=DEV)
+        er = torch.full((N,), -7, dtype=torch.int64, device=DEV)
+        return data, off, (src, in_off, out_off, dst, ol, er if direction == D else None)
+
+    def check(data, off, args):
+        g.launch()
+        torch.cuda.synchronize()
+        if direction == E:
+            want, _, wl = oracle.encode_batch(data, off)
+            assert np.array_equal(host(args[4]), wl) and np.array_equal(host(args[3])[:want.size], want)
+        else:
+            _, _, wl, we = oracle.decode_batch(data, off)
+            assert np.array_equal(host(args[4]), wl) and np.array_equal(host(args[5]), we)
+            assert (we >= 0).sum() > 0
+
+    small = batch(3000)
+    g = BatchGraph(direction, *small[2])
+    check(*small)
+    big = batch(1_200_000)
+    g.update(*big[2])
+    for _ in range(2):
+        check(*big)
+    small2 = batch(2000)
+    g.update(*small2[2])
+    check(*small2)
+    g.close()
+
+
 def _small_trace(n_target, rate, hi, seed, corrupt=0.05):
     tr = workloads.serving_trace(rate=rate, seconds=n_target / rate, lo=64, hi=hi, seed=seed, corrupt_frac=corrupt)
     return tr

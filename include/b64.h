@@ -38,7 +38,8 @@
  *     b64_last_error() describes the most recent failure on this thread.
  *   - Entry points allocate no device memory, except:
  *       b64_decode / b64_decode_ex: on first use on a thread and device,
- *         a 64-byte result slot and a pinned readback word, then reused;
+ *         a 64-byte result slot and two 16-byte pinned host buffers (one of
+ *         them written by the decode kernel directly), then reused;
  *       b64_decode_ws: per thread and device, its verdict slots (once) and
  *         a workspace grown to the largest input seen;
  *       b64_graph_create_batch: a private capture stream and the graph;

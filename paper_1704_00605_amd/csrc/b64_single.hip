@@ -259,11 +259,19 @@ Shape g_single[2] = {512, 256};
 // Per-thread, per-device verdict slots of the synchronous decode: d[0]
 // length, d[1] first offending index (written by every call), and the pinned
 // host words they are read back into.
+// Per thread and device: device slots and a pinned readback pair for the
+// two-launch decode (its verdict is formed by atomics in device memory), and
+// a coherent pinned pair (hc, at device address hc_dev) that the one-launch
+// decodes write their verdict to directly (two plain stores, no copy back).
 struct SyncSlot {
     int dev = -1;
     int64_t *d = nullptr;
     int64_t *h = nullptr;
+    int64_t *hc = nullptr;
+    int64_t *hc_dev = nullptr;
 };
+// Value of a verdict word that the decode has not written yet.
+constexpr int64_t VERDICT_UNSET = INT64_MIN;
 thread_local std::vector<SyncSlot> t_slots;
 
 int sync_slot(SyncSlot **out)
@@ -277,7 +285,10 @@ int sync_slot(SyncSlot **out)
     s.dev = dev;
     hipError_t e = hipMalloc((void **)&s.d, 64);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s.h, 16, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.hc, 16, hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&s.hc_dev, s.hc, 0);
     if (e != hipSuccess) {
+        if (s.hc) (void)hipHostFree(s.hc);
         if (s.h) (void)hipHostFree(s.h);
         if (s.d) (void)hipFree(s.d);
         return b64i_fail(B64_HIP_ERROR, "synchronous-call slots: %s", hipGetErrorString(e));
@@ -504,11 +515,18 @@ int decode_small(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t 
 //     k_dec_single, which forms the verdict itself;
 //   - otherwise, at most SMALL_UNITS interior units: one workgroup;
 //   - otherwise the slot initialisation and k_dec_single.
+//   The one-launch paths write the verdict with two plain stores; given
+//   `direct` (a device-visible pair, such as coherent pinned host memory)
+//   they write it there instead of d_len / d_err, and *used_direct says
+//   which pair holds the verdict. The two-launch path forms it by atomics on
+//   d_len / d_err, which stay in device memory.
 int decode_with_verdict(const uint8_t *src, int64_t n, uint8_t *dst, int mode, int64_t *d_len,
-                        int64_t *d_err, hipStream_t s)
+                        int64_t *d_err, hipStream_t s, int64_t *direct = nullptr, bool *used_direct = nullptr)
 {
+    int64_t *const l1 = direct ? direct : d_len, *const e1 = direct ? direct + 1 : d_err;
+    if (used_direct) *used_direct = direct != nullptr;
     const int64_t units = (n - 1) / 16;
-    if (units <= SMALL_UNITS_CELL) return decode_small(src, n, dst, mode, d_len, d_err, s);
+    if (units <= SMALL_UNITS_CELL) return decode_small(src, n, dst, mode, l1, e1, s);
     if (VerdictCell *cell = stream_cell(s)) {
         int block, upl, grid, cus;
         int rc = single_grid(1, units, &block, &upl, &grid);
@@ -523,23 +541,24 @@ int decode_with_verdict(const uint8_t *src, int64_t n, uint8_t *dst, int mode, i
             const int map = g_single[1].map.load();
             switch (align_class(src, dst)) {
             case 0:
-                launch_dec_single<0, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, d_len,
-                                           d_err, s);
+                launch_dec_single<0, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, l1,
+                                           e1, s);
                 break;
             case 1:
-                launch_dec_single<1, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, d_len,
-                                           d_err, s);
+                launch_dec_single<1, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, l1,
+                                           e1, s);
                 break;
             default:
-                launch_dec_single<2, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, d_len,
-                                           d_err, s);
+                launch_dec_single<2, true>(upl, map, grid, block, src, n, dst, mode, nullptr, nullptr, cell, l1,
+                                           e1, s);
                 break;
             }
             LAUNCH_TRY();
             return B64_OK;
         }
     }
-    if (units <= SMALL_UNITS) return decode_small(src, n, dst, mode, d_len, d_err, s);
+    if (units <= SMALL_UNITS) return decode_small(src, n, dst, mode, l1, e1, s);
+    if (used_direct) *used_direct = false;
     return decode_two_launches(src, n, dst, mode, d_len, d_err, s);
 }
 
@@ -584,11 +603,25 @@ int64_t b64_decode_ex(const uint8_t *src, int64_t n, uint8_t *dst, int64_t *err_
     rc = sync_slot(&sl);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    rc = decode_with_verdict(src, n, dst, mode, sl->d, sl->d + 1, s);
+    volatile int64_t *const hv = sl->hc;
+    hv[0] = VERDICT_UNSET;
+    hv[1] = VERDICT_UNSET;
+    bool direct = false;
+    rc = decode_with_verdict(src, n, dst, mode, sl->d, sl->d + 1, s, sl->hc_dev, &direct);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(sl->h, sl->d, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int64_t len = sl->h[0], err = sl->h[1];
+    int64_t len, err;
+    if (direct) {  // the verdict lands in host memory: only the wait is left
+        HIP_TRY(hipStreamSynchronize(s));
+        len = hv[0];
+        err = hv[1];
+        if (len == VERDICT_UNSET || err == VERDICT_UNSET)
+            return b64i_fail(B64_HIP_ERROR, "decode finished without a verdict in host memory");
+    } else {
+        HIP_TRY(hipMemcpyAsync(sl->h, sl->d, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        len = sl->h[0];
+        err = sl->h[1];
+    }
     if (len < 0) {
         *err_off = err;
         return b64i_fail(B64_INVALID_INPUT, "invalid base64 input at offset %lld", (long long)err);

@@ -256,13 +256,12 @@ struct Shape {
 };
 Shape g_single[2] = {512, 256};
 
-// Per-thread, per-device verdict slots of the synchronous decode: d[0]
-// length, d[1] first offending index (written by every call), and the pinned
-// host words they are read back into.
-// Per thread and device: device slots and a pinned readback pair for the
-// two-launch decode (its verdict is formed by atomics in device memory), and
-// a coherent pinned pair (hc, at device address hc_dev) that the one-launch
-// decodes write their verdict to directly (two plain stores, no copy back).
+// Per-thread, per-device verdict slots of the synchronous decode, each a
+// (length, first offending index) pair written by every call: device slots d
+// with the pinned pair h they are read back into, for the two-launch decode
+// (its verdict is formed by atomics in device memory), and a coherent pinned
+// pair hc (device address hc_dev) that the one-launch decodes write their
+// verdict to directly (two plain stores, no copy back).
 struct SyncSlot {
     int dev = -1;
     int64_t *d = nullptr;

@@ -74,6 +74,7 @@ def test_argument_errors_need_no_gpu(L):
     assert L.b64_decode_ws(None, 4, None, ctypes.byref(err), _lib.MODE_STRICT, None) == _lib.BAD_ARG
     assert L.b64_decode_ws(None, 1 << 38, None, ctypes.byref(err), 0, None) == _lib.BAD_ARG
     assert L.b64_decode_ws_async(None, 8, None, 0, None, None, None, 0, None) == _lib.BAD_ARG
+    assert L.b64_decode_ws_async(None, 0, None, 0, None, None, None, 0, None) == _lib.BAD_ARG  # empty input, no slots
     for d, m in ((0, 3), (1, 2), (0, -1)):
         assert L.b64_set_single_tune(d, ctypes.byref(_lib.Tune(block=0, units_per_lane=0, grid=0, layout=m))) == _lib.BAD_ARG
     assert L.b64_set_single_tune(0, ctypes.byref(_lib.Tune(block=0, units_per_lane=0, grid=0, layout=0))) == 0
